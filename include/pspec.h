@@ -1,0 +1,188 @@
+/*
+ * pspec -- graph p-Laplacian hot path of p-spectral clustering on the Grassmann manifold,
+ * for AMD Instinct MI355X (gfx950).  C ABI of libpspec.so.
+ *
+ * The method (Pasadakis, Schenk, Vlacic, Yzelman, "Nonlinear spectral clustering with C++
+ * GraphBLAS", Section 2) minimises, over U in Gr(k, n),
+ *
+ *     F_p(U) = sum_l sum_{i,j} w_ij |u_i^l - u_j^l|^p / (2 ||u^l||_p^p),   p in (1, 2]   (Eq. (1))
+ *
+ * with (Delta_p u)_i = sum_j w_ij phi_p(u_i - u_j), phi_p(x) = |x|^(p-1) sign(x) and
+ * ||u||_p^p = sum_i |u_i|^p (Section 2), by Newton's method with truncated CG, which needs the
+ * gradient (the EucGrad callback) and Hessian-vector products (the EucHessianEta callback,
+ * Algorithm 1).  This library evaluates those callbacks and the Grassmann projection and
+ * retraction around them on the GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Graph.   Symmetric CSR with both directions of every edge stored: rowptr (int64, n+1,
+ *          rowptr[0] = 0, non-decreasing, rowptr[n] = nnz), col (int32, nnz, 0 <= col < n) and w
+ *          (nnz weights, w_ij = w_ji, w > 0).  Self-loops contribute nothing (x = 0) and are allowed.
+ * Blocks.  U, V, G, HV, Z, ... are n x k, ROW-MAJOR with leading dimension ld >= k (element (i, l)
+ *          at ptr[i*ld + l]); column l is the vector u^l of Eq. (1).  The paper's eta is k x n;
+ *          the transpose is used here so that one edge touches k contiguous values.  Passing U and V
+ *          as the two halves of one n x 2k array (ldu = ldv = 2k, V = U + k) is supported and makes
+ *          each neighbour gather a single contiguous 2k-value row.
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller, unless stated otherwise.
+ *          Scalar results (F, F_col, M) are FP64 device arrays, so the caller decides when to copy.
+ * Streams. Every call enqueues its kernels on `stream` and returns without synchronising, except
+ *          pspec_graph_create (which synchronises `stream` once, see there).  `stream` may be NULL
+ *          (the null stream).  A graph handle holds the scratch of its calls: at most one call per
+ *          handle may be in flight at a time.
+ * Types.   dt = PSPEC_F32: U/V/G/HV are float; edge arithmetic in FP32 (|x|^(p-2) via the hardware
+ *          exp2/log2), every reduction (numerators, p-norms, dot products, Gram matrices) in FP64.
+ *          dt = PSPEC_F64: everything double, |x|^(p-2) via the device-library pow().
+ * Errors.  Argument errors are found on the host before anything is launched and return
+ *          PSPEC_ERR_ARG (PSPEC_ERR_UNSUPPORTED for valid but unsupported requests); a failed HIP
+ *          call returns PSPEC_ERR_HIP.  pspec_last_error() describes the last failure of the
+ *          calling thread.  A column with ||u^l||_p = 0 makes F_l undefined: F_l and that column of
+ *          G and HV come out NaN (IEEE propagation); this is not reported as an error.
+ * Near 0.  The singularity of |x|^(p-2) at x = 0 in the Hessian is removed with the caller's eps:
+ *          psi(x) = max(|x|, eps)^(p-2), applied to the edge terms and to the diagonal p-norm term.
+ *          phi_p and |x|^p are evaluated exactly (0 at x = 0).  The FP32 path evaluates
+ *          |x|^(p-2) at max(|x|, 2^-64), which changes nothing for exact zeros and only affects
+ *          differences 0 < |x| < 2^-64.
+ */
+#ifndef PSPEC_H
+#define PSPEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSPEC_OK = 0,
+    PSPEC_ERR_ARG = 1,         /* invalid argument (detected on the host, nothing launched) */
+    PSPEC_ERR_UNSUPPORTED = 2, /* valid but outside what this build supports (e.g. k > 64) */
+    PSPEC_ERR_HIP = 3,         /* a HIP runtime call failed */
+    PSPEC_ERR_WORKSPACE = 4    /* the caller's workspace is too small */
+} pspec_status;
+
+typedef enum { PSPEC_F32 = 0, PSPEC_F64 = 1 } pspec_dtype;
+
+/* Opaque handle: a CSR graph (borrowed) plus its row schedule and scratch (owned). */
+typedef struct pspec_graph_s *pspec_graph;
+
+/* The stream type is HIP's hipStream_t; declared opaquely so this header needs no HIP headers. */
+typedef struct ihipStream_t *pspec_stream;
+
+/* Largest k supported by the kernels of this build. */
+#define PSPEC_K_MAX 64
+
+/*
+ * pspec_graph_create -- build the row schedule of a graph (degree binning).
+ *   n, nnz          nodes and stored nonzeros (n >= 1, nnz >= 0).
+ *   rowptr, col, w  device CSR arrays as described above; BORROWED: they must stay valid and
+ *                   unchanged until pspec_graph_destroy.
+ *   wtype           element type of w.  F32 calls need PSPEC_F32 weights; F64 calls accept
+ *                   either (FP32 weights are promoted exactly).
+ *   k_max           largest k any later call on this handle will use (1..PSPEC_K_MAX).
+ *   stream          the schedule is built on this stream; the call synchronises it once to read
+ *                   back the sizes of the schedule.
+ *   out             receives the handle.
+ * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed one
+ * wavefront-group per row in node order; longer rows are cut into chunks of at most
+ * PSPEC_CHUNK edges, each processed by a whole workgroup, and rows spanning several chunks are
+ * combined in a fixed order afterwards, so every result is bit-reproducible.  The CSR is
+ * validated on the device (rowptr monotone with rowptr[0] = 0 and rowptr[n] = nnz, every column
+ * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  The handle allocates its own device
+ * memory (schedule, per-tile FP64 partial sums, chunk scratch): about
+ * 8 * 4 * k_max * (n / 256 + chunks) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
+ */
+#define PSPEC_LIGHT_MAX 1024
+#define PSPEC_CHUNK 2048
+pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                                const void *w, pspec_dtype wtype, int k_max, pspec_stream stream,
+                                pspec_graph *out);
+
+/* Releases the handle's device memory (synchronises the device first).  NULL is a no-op. */
+pspec_status pspec_graph_destroy(pspec_graph g);
+
+/* Schedule statistics: rows above PSPEC_LIGHT_MAX, chunks, rows spanning several chunks. */
+pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int64_t *chunks, int64_t *split_rows);
+
+/*
+ * pspec_objective -- Eq. (1).  F_col[l] = N_l / D_l with N_l = (1/2) sum over stored edges of
+ * w_ij |u_i^l - u_j^l|^p and D_l = ||u^l||_p^p; *F = sum_l F_col[l].
+ *   U      n x k block (dt), leading dimension ldu.
+ *   F_col  device, k doubles, may be NULL;  F  device, 1 double, may be NULL.
+ */
+pspec_status pspec_objective(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, double p,
+                             double *F_col, double *F, pspec_stream stream);
+
+/*
+ * pspec_grad -- Euclidean gradient of Eq. (1) (the EucGrad callback of Section 2):
+ *   G[i, l] = (p / D_l) ((Delta_p u^l)_i - F_l phi_p(u_i^l)).
+ *   G      n x k output (dt), leading dimension ldg; must not overlap U.
+ *   F_col  device, k doubles (the objective per column, computed on the way), may be NULL.
+ */
+pspec_status pspec_grad(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, double p,
+                        void *G, int64_t ldg, double *F_col, pspec_stream stream);
+
+/*
+ * pspec_hvp -- Hessian-vector product of Eq. (1) (the EucHessianEta callback, Algorithm 1), fused
+ * with the gradient, in one pass over the edges:
+ *   HV[:, l] = H^l(U) V[:, l] where, with D = D_l, F = F_l, g = G[:, l], phi = phi_p(u^l),
+ *   (H v)_i = (p/D) [ (p-1) sum_j w_ij psi(u_i - u_j)(v_i - v_j) - F (p-1) psi(u_i) v_i
+ *                     - g_i (phi^T v) - phi_i (g^T v) ]
+ *   (the exact Hessian of Eq. (1): Algorithm 1's diag(H^l) eta - (diag(H^l) - H^l) eta).
+ *   V      n x k direction (dt), leading dimension ldv (may be U + k with ldu = ldv, see above).
+ *   eps    > 0, the cap of psi (see "Near 0").
+ *   HV, G  n x k outputs (dt); G is REQUIRED (the gradient is a by-product of the pass); neither
+ *          may overlap U, V or each other.
+ *   F_col  device, k doubles, may be NULL.
+ */
+pspec_status pspec_hvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                       int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
+                       double *F_col, pspec_stream stream);
+
+/*
+ * Dense n x k operations of the Grassmann geometry (the manifold of Section 2; the formulas are
+ * the standard ones of the Edelman-Arias-Smith geometry the paper cites).  They need a caller
+ * workspace of pspec_dense_workspace_bytes(k) bytes (device, 256-byte aligned); one call per
+ * workspace may be in flight at a time.
+ */
+size_t pspec_dense_workspace_bytes(int k);
+
+/*
+ * pspec_project -- tangent projection at U (orthonormal columns):
+ *   M   = U^T Z                                  (k x k, FP64, row-major, written if M != NULL)
+ *   out = Z - U M - X MX                         (the X MX term only if X != NULL)
+ * With X = eta and MX = U^T G this gives the Riemannian Hessian P_U(H eta) - eta (U^T G).
+ *   MX   device k x k FP64 row-major (required when X != NULL).
+ *   out  may be the same array as Z (same ld); must not overlap U or X otherwise.
+ */
+pspec_status pspec_project(int64_t n, int k, pspec_dtype dt, const void *U, int64_t ldu, const void *Z,
+                           int64_t ldz, const void *X, int64_t ldx, const double *MX, void *out, int64_t ldo,
+                           double *M, void *ws, size_t ws_bytes, pspec_stream stream);
+
+/*
+ * pspec_retract -- QR retraction: Uout = qf(U + t eta), the Q factor of the thin QR
+ * factorisation with a positive diagonal of R, computed as Cholesky-QR in FP64: R = chol(Y^T Y),
+ * Q = Y R^-1.  Uout may be the same array as U (same ld).  If Y is numerically rank deficient the
+ * Cholesky factorisation breaks down and Uout is NaN.
+ *   R  device k x k FP64 row-major upper-triangular factor (written if not NULL).
+ */
+pspec_status pspec_retract(int64_t n, int k, pspec_dtype dt, const void *U, int64_t ldu, const void *eta,
+                           int64_t lde, double t, void *Uout, int64_t ldo, double *R, void *ws, size_t ws_bytes,
+                           pspec_stream stream);
+
+/* pspec_dot -- *out = sum_{i,l} A[i,l] B[i,l] (Frobenius inner product, FP64, fixed order). */
+pspec_status pspec_dot(int64_t n, int k, pspec_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb,
+                       double *out, void *ws, size_t ws_bytes, pspec_stream stream);
+
+/* pspec_axpby -- Y = alpha X + beta Y (elementwise, n x k; beta = 0 ignores Y's old contents). */
+pspec_status pspec_axpby(int64_t n, int k, pspec_dtype dt, double alpha, const void *X, int64_t ldx, double beta,
+                         void *Y, int64_t ldy, pspec_stream stream);
+
+/* Message describing the last non-OK status returned on the calling thread ("" if none). */
+const char *pspec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSPEC_H */

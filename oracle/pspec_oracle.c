@@ -33,6 +33,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* phi_p(x) = |x|^(p-1) sign(x), with sign(0) = 0 (Section 2). */
 static double phi_p(double x, double p)

@@ -1,0 +1,80 @@
+"""The C-ABI library loads on the CPU and exports every entry point declared in include/pspec.h.
+
+No compute call is made here (there is no GPU); argument validation that returns before any
+launch is exercised where it needs no device memory.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pspec.h")
+LIB = os.path.join(ROOT, "paper_2605_26975_amd", "libpspec.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pspec_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def libpspec():
+    if not os.path.exists(LIB):
+        pytest.fail("libpspec.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("pspec_graph_create", "pspec_objective", "pspec_grad", "pspec_hvp", "pspec_project",
+                 "pspec_retract"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(libpspec):
+    missing = [n for n in declared_functions() if not hasattr(libpspec, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    from paper_2605_26975_amd import pspec
+
+    assert sorted(pspec.exported_symbols()) == declared_functions()
+
+
+def test_host_side_argument_errors(libpspec):
+    """Errors found before any launch: NULL output handle, bad sizes, bad k, NULL graph."""
+    vp = ctypes.c_void_p
+    libpspec.pspec_graph_create.argtypes = [ctypes.c_int64, ctypes.c_int64, vp, vp, vp, ctypes.c_int, ctypes.c_int,
+                                            vp, ctypes.POINTER(vp)]
+    libpspec.pspec_graph_create.restype = ctypes.c_int
+    libpspec.pspec_last_error.restype = ctypes.c_char_p
+    h = vp()
+    assert libpspec.pspec_graph_create(0, 0, 1, 1, 1, 0, 4, None, ctypes.byref(h)) == 1
+    assert b"n = 0" in libpspec.pspec_last_error()
+    assert libpspec.pspec_graph_create(10, -1, 1, 1, 1, 0, 4, None, ctypes.byref(h)) == 1
+    assert libpspec.pspec_graph_create(10, 5, None, 1, 1, 0, 4, None, ctypes.byref(h)) == 1
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 65, None, ctypes.byref(h)) == 2
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, None, None) == 1
+    libpspec.pspec_objective.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, ctypes.c_double, vp, vp,
+                                         vp]
+    libpspec.pspec_objective.restype = ctypes.c_int
+    assert libpspec.pspec_objective(None, 0, 4, 1, 4, 1.5, None, None, None) == 1
+    assert b"NULL graph" in libpspec.pspec_last_error()
+
+
+def test_dense_argument_errors(libpspec):
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    libpspec.pspec_dense_workspace_bytes.argtypes = [i32]
+    libpspec.pspec_dense_workspace_bytes.restype = ctypes.c_size_t
+    assert libpspec.pspec_dense_workspace_bytes(16) >= 512 * 16 * 16 * 8
+    libpspec.pspec_retract.argtypes = [i64, i32, i32, vp, i64, vp, i64, dbl, vp, i64, vp, vp, ctypes.c_size_t, vp]
+    libpspec.pspec_retract.restype = ctypes.c_int
+    # n < k, ld < k, k > 64, tiny workspace: all rejected on the host
+    assert libpspec.pspec_retract(3, 4, 0, 256, 4, 512, 4, 0.1, 768, 4, None, 1024, 1 << 30, None) == 1
+    assert libpspec.pspec_retract(100, 4, 0, 256, 3, 512, 4, 0.1, 768, 4, None, 1024, 1 << 30, None) == 1
+    assert libpspec.pspec_retract(100, 65, 0, 256, 65, 512, 65, 0.1, 768, 65, None, 1024, 1 << 30, None) == 2
+    assert libpspec.pspec_retract(100, 4, 0, 256, 4, 512, 4, 0.1, 768, 4, None, 1024, 16, None) == 4

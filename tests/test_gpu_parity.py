@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Tolerances.  FP64 path: 1e-11 relative (only the order of FP64 sums and libm-vs-device pow()
+differ).  FP32 path: 1e-5 relative on F and on the gradient (Frobenius over the block), the
+stated target; the Hessian-vector product is held to 1e-4 (its edge weights |x|^(p-2) are up to
+eps^(p-2) ~ 1e7 at p near 1, and it carries the FP32 rounding of the gradient through its
+rank-2 terms).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_26975_amd import gen
+from paper_2605_26975_amd import pspec
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL_F = 1e-5
+F32_TOL_G = 1e-5
+F32_TOL_HV = 1e-4
+F64_TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def sbm1000():
+    return gen.sbm_bernoulli(1000, 4, 0.05, 0.002)
+
+
+@pytest.mark.parametrize("p", [2.0, 1.6, 1.3, 1.1])
+def test_sbm1000_fp64_plain_path(sbm1000, p):
+    print(f"[case] sbm1000 f64 p={p}", flush=True)
+    e = gu.compare(sbm1000, 4, p, 1e-8, torch.float64)
+    assert e["F"] < F64_TOL and e["Fcol"] < F64_TOL, e
+    assert e["G"] < F64_TOL and e["HV"] < F64_TOL, e
+    assert e["objective_matches_hvp"]
+
+
+@pytest.mark.parametrize("p", [2.0, 1.6, 1.3, 1.1])
+def test_sbm1000_fp32_fused_path(sbm1000, p):
+    print(f"[case] sbm1000 f32 p={p}", flush=True)
+    e = gu.compare(sbm1000, 4, p, 1e-8, torch.float32)
+    print(e)
+    assert e["F"] < F32_TOL_F and e["Fcol"] < F32_TOL_F, e
+    assert e["G"] < F32_TOL_G, e
+    assert e["HV"] < F32_TOL_HV, e
+
+
+@pytest.mark.parametrize("k", [1, 3, 16, 33])
+def test_multitile_ragged(k):
+    """50,000 nodes (195 full tiles and a ragged one), k from 1 to 33 (padded column lanes)."""
+    print(f"[case] sbm50k k={k}", flush=True)
+    g = gen.sbm_edges(50_000, 16, 270_000, 30_000, 0.5, 1.5, seed=7)
+    for dtype, tol in ((torch.float32, F32_TOL_G), (torch.float64, F64_TOL)):
+        e = gu.compare(g, k, 1.3, 1e-8, dtype)
+        assert e["F"] < tol and e["G"] < tol, (dtype, e)
+        assert e["HV"] < (F32_TOL_HV if dtype == torch.float32 else F64_TOL), (dtype, e)
+
+
+def _hub_graph():
+    """Light rows plus hubs of degree 1024 (light limit), 1025, 1500 (one heavy chunk) and 5000
+    (three chunks, combined afterwards)."""
+    rng = np.random.default_rng(5)
+    n = 6000
+    i = [rng.integers(0, n, 30000)]
+    j = [rng.integers(0, n, 30000)]
+    for hub, deg in ((0, 5000), (1, 1500), (2, 1024), (3, 1025)):
+        nb = rng.choice(np.arange(10, n), size=deg, replace=False)
+        i.append(np.full(deg, hub))
+        j.append(nb)
+    i = np.concatenate(i)
+    j = np.concatenate(j)
+    g = gen.csr_from_edges(n, i, j, lambda lo, hi: gen.edge_uniform(3, lo, hi, 0.1, 1.0), name="hubs")
+    return g
+
+
+@pytest.mark.parametrize("k", [5, 32])
+def test_heavy_and_split_rows(k):
+    print(f"[case] hubs k={k}", flush=True)
+    g = _hub_graph()
+    dg = gu.device_graph(g, k)
+    info = dg.info()
+    deg = g.degrees()
+    assert info["heavy_rows"] == int(np.sum(deg > pspec.LIGHT_MAX))
+    assert info["split_rows"] == int(np.sum(deg > pspec.CHUNK))
+    assert info["chunks"] == int(np.sum(np.where(deg > pspec.LIGHT_MAX, (deg + pspec.CHUNK - 1) // pspec.CHUNK, 0)))
+    assert info["split_rows"] >= 1 and info["heavy_rows"] >= 3
+    for dtype, tol in ((torch.float64, F64_TOL), (torch.float32, F32_TOL_G)):
+        e = gu.compare(g, k, 1.2, 1e-8, dtype, dg=dg)
+        assert e["F"] < tol and e["G"] < tol, (dtype, e)
+        assert e["HV"] < (F32_TOL_HV if dtype == torch.float32 else F64_TOL), (dtype, e)
+
+
+def test_rmat_scale14_p105():
+    """Skewed degrees (R-MAT), k = 32, p = 1.05, eps = 1e-8."""
+    print("[case] rmat14", flush=True)
+    g = gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9)
+    e32 = gu.compare(g, 32, 1.05, 1e-8, torch.float32)
+    print(e32)
+    assert e32["F"] < F32_TOL_F and e32["G"] < F32_TOL_G and e32["HV"] < F32_TOL_HV, e32
+    e64 = gu.compare(g, 32, 1.05, 1e-8, torch.float64)
+    assert e64["F"] < F64_TOL and e64["G"] < F64_TOL and e64["HV"] < F64_TOL, e64
+
+
+def test_knn_graph_p13():
+    print("[case] knn20k", flush=True)
+    g = gen.knn_mixture(20_000, 8, 10, 1.0, 20.0, seed=4)
+    e = gu.compare(g, 8, 1.3, 1e-8, torch.float32)
+    assert e["F"] < F32_TOL_F and e["G"] < F32_TOL_G and e["HV"] < F32_TOL_HV, e
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_empty_graph_and_single_node(dtype):
+    print(f"[case] empty {dtype}", flush=True)
+    for n in (1, 300):
+        g = gen.Graph(n=n, rowptr=np.zeros(n + 1, np.int64), col=np.zeros(0, np.int32), w=np.zeros(0, np.float32))
+        U, V = gu.inputs(n, 4)
+        dg = gu.device_graph(g, 4)
+        HV, G, Fc = gu.gpu_hvp(dg, U, V, 1.5, 1e-8, dtype)
+        assert np.all(Fc == 0.0) and np.all(G == 0.0) and np.all(HV == 0.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_disconnected_indicators_are_exact_zeros(dtype):
+    """Per-component constant columns: every x = 0, so F = 0 and G = 0 exactly (a zero-difference
+    edge must contribute exactly nothing)."""
+    print(f"[case] indicators {dtype}", flush=True)
+    g = gen.sbm_bernoulli(400, 2, 0.1, 0.0, seed=3)
+    U = np.zeros((400, 3), np.float32)
+    U[:200, 0] = 1.0
+    U[200:, 1] = 1.0
+    U[:200, 2] = 2.0
+    U[200:, 2] = -0.5
+    V = gen.block(400, 3, 2)
+    dg = gu.device_graph(g, 3)
+    for p in (2.0, 1.5, 1.05):
+        HV, G, Fc = gu.gpu_hvp(dg, U, V, p, 1e-8, dtype)
+        assert np.all(Fc == 0.0) and np.all(G == 0.0)
+        HVo, _, _ = gu.oracle_hvp(g, U, V, p, 1e-8)
+        assert gu.rel(HV, HVo) < (F32_TOL_HV if dtype == torch.float32 else F64_TOL)
+
+
+def test_zero_column_is_nan():
+    g = gen.sbm_bernoulli(300, 2, 0.1, 0.01, seed=3)
+    U, V = gu.inputs(300, 3)
+    U[:, 1] = 0.0
+    HV, G, Fc = gu.gpu_hvp(gu.device_graph(g, 3), U, V, 1.5, 1e-8, torch.float32)
+    assert np.isnan(Fc[1]) and np.all(np.isnan(G[:, 1])) and np.all(np.isnan(HV[:, 1]))
+    assert np.all(np.isfinite(G[:, [0, 2]])) and np.all(np.isfinite(HV[:, [0, 2]]))
+
+
+def test_interleaved_and_padded_layouts_match():
+    """U and V as the two halves of one n x 2k array, and blocks with ld > k, give bit-identical
+    results to the plain layout (same arithmetic in the same order)."""
+    g = gen.sbm_edges(20_000, 8, 100_000, 10_000, 0.5, 1.5, seed=11)
+    k = 16
+    U, V = gu.inputs(g.n, k)
+    dg = gu.device_graph(g, k)
+    Ut = torch.as_tensor(U).cuda()
+    Vt = torch.as_tensor(V).cuda()
+    HV0, G0, F0 = pspec.hvp(dg, Ut, Vt, 1.1, 1e-8)
+    P = torch.cat([Ut, Vt], dim=1).contiguous()
+    HV1, G1, F1 = pspec.hvp(dg, P[:, :k], P[:, k:], 1.1, 1e-8)
+    big = torch.zeros((g.n, 24), dtype=torch.float32, device="cuda")
+    big[:, :k] = Ut
+    bigV = torch.zeros((g.n, 20), dtype=torch.float32, device="cuda")
+    bigV[:, :k] = Vt
+    HVo = torch.zeros((g.n, 40), dtype=torch.float32, device="cuda")
+    Go = torch.zeros((g.n, 17), dtype=torch.float32, device="cuda")
+    HV2, G2, F2 = pspec.hvp(dg, big[:, :k], bigV[:, :k], 1.1, 1e-8, HV=HVo[:, 3:3 + k], G=Go[:, :k])
+    torch.cuda.synchronize()
+    for a, b in ((HV0, HV1), (G0, G1), (F0, F1), (HV0, HV2), (G0, G2), (F0, F2)):
+        assert torch.equal(a, b)
+    assert torch.all(HVo[:, :3] == 0) and torch.all(HVo[:, 3 + k:] == 0) and torch.all(Go[:, k:] == 0)
+
+
+def test_deterministic():
+    g = gen.rmat(13, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=2)
+    U, V = gu.inputs(g.n, 8)
+    dg = gu.device_graph(g, 8)
+    a = gu.gpu_hvp(dg, U, V, 1.2, 1e-8, torch.float32)
+    b = gu.gpu_hvp(dg, U, V, 1.2, 1e-8, torch.float32)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_objective_and_grad_entry_points_agree_with_hvp():
+    g = gen.sbm_edges(30_000, 8, 150_000, 15_000, 0.5, 1.5, seed=12)
+    k = 8
+    U, V = gu.inputs(g.n, k)
+    dg = gu.device_graph(g, k)
+    Ut, Vt = torch.as_tensor(U).cuda(), torch.as_tensor(V).cuda()
+    HV, G, Fc = pspec.hvp(dg, Ut, Vt, 1.4, 1e-8)
+    G2, Fc2 = pspec.grad(dg, Ut, 1.4)
+    F3, Fc3 = pspec.objective(dg, Ut, 1.4)
+    torch.cuda.synchronize()
+    assert torch.equal(G, G2) and torch.equal(Fc, Fc2) and torch.equal(Fc, Fc3)
+    assert float(F3) == pytest.approx(float(Fc.sum()), rel=1e-15)
+
+
+def test_invalid_csr_and_arguments_are_rejected():
+    n = 100
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    rowptr[1:] = 2
+    rowptr[-1] = 2
+    col = torch.tensor([5, 100], dtype=torch.int32, device="cuda")  # 100 is out of range
+    w = torch.ones(2, dtype=torch.float32, device="cuda")
+    rowptr[1:] = 2
+    with pytest.raises(pspec.PSpecError) as ei:
+        pspec.Graph(rowptr, col, w, 4)
+    assert ei.value.status == 1
+    bad_rp = torch.tensor([0, 3, 2] + [2] * (n - 2), dtype=torch.int64, device="cuda")
+    with pytest.raises(pspec.PSpecError):
+        pspec.Graph(bad_rp, torch.tensor([1, 2], dtype=torch.int32, device="cuda"), w, 4)
+    g = gen.sbm_bernoulli(200, 2, 0.1, 0.01)
+    dg = gu.device_graph(g, 4)
+    U = torch.randn(200, 4, device="cuda")
+    for p in (1.0, 2.5, float("nan")):
+        with pytest.raises(pspec.PSpecError):
+            pspec.objective(dg, U, p)
+    with pytest.raises(pspec.PSpecError):
+        pspec.hvp(dg, U, U, 1.5, 0.0)
+    with pytest.raises(pspec.PSpecError):
+        pspec.objective(dg, torch.randn(200, 5, device="cuda"), 1.5)  # k > k_max
+    with pytest.raises(pspec.PSpecError):
+        pspec.hvp(dg, U, U, 1.5, 1e-8, HV=U)  # output overlaps input
+    dg64 = pspec.Graph.from_host(g, "cuda", k_max=4, weight_dtype=torch.float64)
+    with pytest.raises(pspec.PSpecError) as ei:
+        pspec.objective(dg64, U, 1.5)  # FP32 arithmetic with FP64 weights
+    assert ei.value.status == 2
+    F, _ = pspec.objective(dg64, U.double(), 1.5)
+    assert torch.isfinite(F)
+
+
+# --- Grassmann steps --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("k", [1, 4, 13, 32, 64])
+def test_project_and_retract_vs_oracle(dtype, k):
+    import oracle as orc
+
+    print(f"[case] dense {dtype} k={k}", flush=True)
+    rng = np.random.default_rng(k)
+    n = 5000 + k
+    U64, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    Z64 = rng.standard_normal((n, k))
+    X64 = rng.standard_normal((n, k))
+    U = torch.as_tensor(U64).to(dtype).cuda()
+    Z = torch.as_tensor(Z64).to(dtype).cuda()
+    X = torch.as_tensor(X64).to(dtype).cuda()
+    Uh = U.double().cpu().numpy()
+    Zh = Z.double().cpu().numpy()
+    Xh = X.double().cpu().numpy()
+    tol = 1e-6 if dtype == torch.float32 else 1e-13
+    out, M = pspec.project(U, Z)
+    ref, Mref = orc.project(Uh, Zh)
+    assert gu.rel(M.cpu().numpy(), Mref) < 1e-12
+    assert gu.rel(out.double().cpu().numpy(), ref) < tol
+    MX = torch.as_tensor(rng.standard_normal((k, k))).cuda()
+    out2, _ = pspec.project(U, Z, X=X, MX=MX)
+    ref2 = ref - Xh @ MX.cpu().numpy()
+    assert gu.rel(out2.double().cpu().numpy(), ref2) < tol
+    Zc = Z.clone()
+    pspec.project(U, Zc, out=Zc)  # in place
+    assert torch.equal(Zc, out)
+    eta = out
+    for t in (0.0, 0.3, 2.0):
+        Q, R = pspec.retract(U, eta, t)
+        Qref = orc.retract(Uh, eta.double().cpu().numpy(), t)
+        Qh = Q.double().cpu().numpy()
+        assert gu.rel(Qh, Qref) < (3e-6 if dtype == torch.float32 else 1e-12), t
+        assert np.max(np.abs(Qh.T @ Qh - np.eye(k))) < (1e-5 if dtype == torch.float32 else 1e-12)
+        Rh = R.cpu().numpy()
+        assert np.all(np.diag(Rh) > 0) and np.all(np.tril(Rh, -1) == 0)
+    d = pspec.dot(Z, X)
+    assert float(d) == pytest.approx(float(np.sum(Zh * Xh)), rel=1e-12)
+    Y = Z.clone()
+    pspec.axpby(0.5, X, -2.0, Y)
+    assert gu.rel(Y.double().cpu().numpy(), 0.5 * Xh - 2.0 * Zh) < (1e-7 if dtype == torch.float32 else 1e-15)
+    Uc = U.clone()
+    pspec.retract(Uc, eta, 0.3, out=Uc)  # in place
+    assert gu.rel(Uc.double().cpu().numpy(), orc.retract(Uh, eta.double().cpu().numpy(), 0.3)) < (
+        3e-6 if dtype == torch.float32 else 1e-12)
