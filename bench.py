@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the p-Laplacian hot path on one MI355X.
+
+Workload (default): stochastic block model with n = 8,000,000 nodes in 16 equal blocks with
+block-contiguous ids, 43.2 M intra-block and 4.8 M inter-block edge draws (mean degree 12,
+~96 M stored nonzeros), weights U[0.5, 1.5); k = 16 columns, p = 1.1, eps = 1e-8; U, V ~ N(0, 1)
+in FP32.  Everything is synthetic and generated here from fixed seeds.
+
+One step = one pass of the whole hot path:
+  pspec_hvp       fused gradient + Hessian-vector product (edge pass, FP64 reductions, epilogue)
+  pspec_project   Riemannian gradient  P_U(G)            (M_G = U^T G)
+  pspec_project   Riemannian Hessian   P_U(HV) - V M_G
+  pspec_retract   qf(U - t P_U(G))    (Cholesky-QR)
+  pspec_objective F_p at the retracted point
+`value` counts nnz * k edge-column updates per step (the gradient+HVP pass only) over the time of
+the whole step.  The roofline object describes the fused edge kernel alone, timed with HIP events
+that the library records around its edge pass on the call's stream.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "p-Laplacian grad+HVP edge·col updates/s, FP32 vs FP64, % HBM peak"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_hvp_sbm8m_traffic.json")
+
+
+def edge_source_hash() -> str:
+    """Hash of the sources that define the fused edge kernel (traffic figures go stale with them)."""
+    h = hashlib.sha256()
+    for f in ("edge.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_26975_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_edge_bytes(n: int, nnz: int, k: int, es: int = 4) -> int:
+    """Fused edge pass, every input read once and every output written once:
+    CSR (col + w per nonzero, rowptr per row), U and V read, raw L and J rows written."""
+    return nnz * (4 + es) + (n + 1) * 8 + n * k * es * 4
+
+
+def stored_traffic(workload: str, layout: str):
+    """HBM bytes per launch of the edge kernel from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != edge_source_hash() or t.get("workload") != workload or t.get("layout") != layout:
+        return None
+    return t.get("bytes_per_launch")
+
+
+class HipEvents:
+    """Raw hipEvent_t pairs from the HIP runtime torch already loaded (the library records them)."""
+
+    def __init__(self, count: int):
+        import ctypes
+
+        self.ct = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.pairs = []
+        for _ in range(count):
+            a, b = ctypes.c_void_p(), ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(a)) or self.hip.hipEventCreate(ctypes.byref(b)):
+                raise RuntimeError("hipEventCreate failed")
+            self.pairs.append((a, b))
+
+    def elapsed_ms(self, i: int) -> float:
+        ms = self.ct.c_float()
+        a, b = self.pairs[i]
+        if self.hip.hipEventElapsedTime(self.ct.byref(ms), a, b):
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        for a, b in self.pairs:
+            self.hip.hipEventDestroy(a)
+            self.hip.hipEventDestroy(b)
+
+
+def cpu_baseline(args):
+    """Time the FP64 oracle (as it stands) on a quarter-scale sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2605_26975_amd import gen
+
+    n = 2_000_000
+    g = gen.sbm_edges(n, 16, 43_200_000 // 4, 4_800_000 // 4, 0.5, 1.5)
+    k = 16
+    U = gen.block(n, k, gen.SEED_U).astype(np.float64)
+    V = gen.block(n, k, gen.SEED_V).astype(np.float64)
+    o = oracle.default()
+    t0 = time.perf_counter()
+    o.hvp(g.rowptr, g.col, g.w.astype(np.float64), U, V, 1.1, 1e-8)
+    dt = time.perf_counter() - t0
+    return {
+        "value": g.nnz * k / dt,
+        "unit": "edge*col updates/s",
+        "cores": o.num_threads(),
+        "kind": "oracle",
+        "sample": f"FP64 oracle grad+HVP (one call) on SBM n={n} (16 blocks, same recipe at 1/4 scale, "
+                  f"nnz={g.nnz}), k=16, p=1.1: {dt:.2f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layout", default="interleaved", choices=["interleaved", "separate"],
+                    help="U and V as the two halves of one n x 2k array, or two n x k arrays")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); run it with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2605_26975_amd import gen, pspec
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = gen.CONFIGS["sbm8m"]
+    k, p, eps = cfg["k"], cfg["p"][0], cfg["eps"]
+    t0 = time.perf_counter()
+    g = cfg["graph"]()
+    print(f"[bench] graph n={g.n} nnz={g.nnz} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    U_h = gen.block(g.n, k, gen.SEED_U)
+    V_h = gen.block(g.n, k, gen.SEED_V)
+    dg = pspec.Graph.from_host(g, dev, k_max=k)
+    n, nnz = g.n, g.nnz
+    del g
+
+    def make_inputs(dtype):
+        if args.layout == "interleaved":
+            P = torch.empty((n, 2 * k), dtype=dtype, device=dev)
+            P[:, :k] = torch.as_tensor(U_h).to(dtype)
+            P[:, k:] = torch.as_tensor(V_h).to(dtype)
+            return P[:, :k], P[:, k:], P
+        U = torch.as_tensor(U_h).to(dtype).to(dev)
+        V = torch.as_tensor(V_h).to(dtype).to(dev)
+        return U, V, None
+
+    def run(dtype, steps, warmup, timed_kernel=True):
+        U, V, keep = make_inputs(dtype)
+        HV = torch.empty((n, k), dtype=dtype, device=dev)
+        G = torch.empty((n, k), dtype=dtype, device=dev)
+        RG = torch.empty((n, k), dtype=dtype, device=dev)
+        RH = torch.empty((n, k), dtype=dtype, device=dev)
+        Un = torch.empty((n, k), dtype=dtype, device=dev)
+        MG = torch.empty((k, k), dtype=torch.float64, device=dev)
+        Fc = torch.empty(k, dtype=torch.float64, device=dev)
+        F = torch.empty((), dtype=torch.float64, device=dev)
+        Fc2 = torch.empty(k, dtype=torch.float64, device=dev)
+        t_step = -1e-3
+
+        def step():
+            pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc)
+            pspec.project(U, G, out=RG, M=MG)
+            pspec.project(U, HV, X=V, MX=MG, out=RH)
+            pspec.retract(U, RG, t_step, out=Un)
+            pspec.objective(dg, Un, p, F_col=Fc2, F=F)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = HipEvents(steps)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        for i in range(steps):
+            if timed_kernel:
+                dg.set_timing_events_raw(*evs.pairs[i])
+            pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc)
+            if timed_kernel:
+                dg.set_timing_events_raw(None, None)
+            pspec.project(U, G, out=RG, M=MG)
+            pspec.project(U, HV, X=V, MX=MG, out=RH)
+            pspec.retract(U, RG, t_step, out=Un)
+            pspec.objective(dg, Un, p, F_col=Fc2, F=F)
+        stop.record()
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        edge_ms = [evs.elapsed_ms(i) for i in range(steps)] if timed_kernel else []
+        evs.close()
+        ok = bool(torch.isfinite(F).item()) and bool(torch.isfinite(HV).all().item())
+        return total_ms / steps, edge_ms, ok
+
+    t32, edge32, ok32 = run(torch.float32, args.steps, args.warmup)
+    print(f"[bench] fp32 step {t32:.3f} ms, edge pass {np.mean(edge32):.3f} ms", file=sys.stderr, flush=True)
+    fp64 = None
+    if not args.no_fp64:
+        t64, edge64, ok64 = run(torch.float64, max(3, args.steps // 4), 1)
+        fp64 = {
+            "ms_per_step": t64,
+            "value": nnz * k / (t64 * 1e-3),
+            "edge_pass_ms": float(np.mean(edge64)),
+            "edge_pass_value": nnz * k / (np.mean(edge64) * 1e-3),
+            "finite": ok64,
+        }
+        print(f"[bench] fp64 step {t64:.3f} ms, edge pass {np.mean(edge64):.3f} ms", file=sys.stderr, flush=True)
+
+    edge_ms = float(np.mean(edge32))
+    alg_bytes = algorithmic_edge_bytes(n, nnz, k)
+    achieved = alg_bytes / (edge_ms * 1e-3) / 1e9
+    traffic = stored_traffic("sbm8m", args.layout)
+    out = {
+        "metric": METRIC,
+        "value": nnz * k / (t32 * 1e-3),
+        "unit": "edge*col updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "sbm8m: SBM n=8,000,000, 16 blocks, mean degree 12, w~U[0.5,1.5], k=16, p=1.1, eps=1e-8",
+            "n": n,
+            "nnz": nnz,
+            "k": k,
+            "p": p,
+            "eps": eps,
+            "layout": args.layout,
+            "step": "hvp(fused grad) + 2x project + retract + objective",
+            "edge_col_updates_per_step": nnz * k,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "edge_light (fused grad+HVP edge pass)",
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "launch_ms": edge_ms,
+        },
+        "edge_pass_value": nnz * k / (edge_ms * 1e-3),
+        "fp64": fp64,
+        "speedup_fp32_over_fp64": (fp64["ms_per_step"] / t32) if fp64 else None,
+        "finite": ok32,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on the sample ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

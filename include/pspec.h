@@ -66,8 +66,9 @@ typedef enum { PSPEC_F32 = 0, PSPEC_F64 = 1 } pspec_dtype;
 /* Opaque handle: a CSR graph (borrowed) plus its row schedule and scratch (owned). */
 typedef struct pspec_graph_s *pspec_graph;
 
-/* The stream type is HIP's hipStream_t; declared opaquely so this header needs no HIP headers. */
+/* HIP's hipStream_t and hipEvent_t, declared opaquely so this header needs no HIP headers. */
 typedef struct ihipStream_t *pspec_stream;
+typedef struct ihipEvent_t *pspec_event;
 
 /* Largest k supported by the kernels of this build. */
 #define PSPEC_K_MAX 64
@@ -103,6 +104,15 @@ pspec_status pspec_graph_destroy(pspec_graph g);
 
 /* Schedule statistics: rows above PSPEC_LIGHT_MAX, chunks, rows spanning several chunks. */
 pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int64_t *chunks, int64_t *split_rows);
+
+/*
+ * Timing hook (for benchmarks).  While set, every pspec_objective / pspec_grad / pspec_hvp call on
+ * this handle records `before` on its stream immediately before the first kernel of the edge pass
+ * and `after` immediately after its last one (light rows, heavy chunks, split-row combine), so
+ * hipEventElapsedTime(before, after) is the duration of the edge pass alone.  The events are
+ * created and owned by the caller; pass NULL for both to stop recording.
+ */
+pspec_status pspec_graph_set_timing_events(pspec_graph g, pspec_event before, pspec_event after);
 
 /*
  * pspec_objective -- Eq. (1).  F_col[l] = N_l / D_l with N_l = (1/2) sum over stored edges of

@@ -76,6 +76,7 @@ struct Graph {
     double *scalars = nullptr;    // device [kScalars * k_max]
     double *chunk_scratch = nullptr;  // device [n_chunks * 2 * k_max] (row partials of split rows)
     void *mem = nullptr;          // the single device allocation holding all of the above
+    hipEvent_t ev_before = nullptr, ev_after = nullptr;  // optional edge-pass timing events
 };
 
 // ---- device helpers ---------------------------------------------------------------------------

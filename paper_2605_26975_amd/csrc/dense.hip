@@ -16,10 +16,26 @@
 namespace pspec {
 namespace {
 
-constexpr int kDenseBlocks = 512;
+constexpr int kDenseBlocks = 1024;  // first-level partials of Gram matrices and dot products
+constexpr int kTreeFan = 32;         // partials summed per thread at each further level
 
-size_t dense_ws_doubles(int k) { return (size_t)kDenseBlocks * k * k + 4 * (size_t)k * k + kDenseBlocks + 64; }
+// Workspace layout (doubles): level-1 partials [kDenseBlocks][k*k], level-2 partials
+// [kDenseBlocks / kTreeFan][k*k], then M, R^-1 (k*k each), plus slack.
+size_t dense_ws_doubles(int k) {
+    const size_t kk = (size_t)k * k;
+    return kDenseBlocks * kk + (kDenseBlocks / kTreeFan) * kk + 2 * kk + 64;
+}
 
+// Rows per LDS tile: 1024 values per matrix for FP32 (4 per thread), 512 for FP64.
+template <typename T, int K>
+constexpr int gram_tile_rows() {
+    return (sizeof(T) == 4 ? 1024 : 512) / K;
+}
+
+// Per-block partial of M = A^T B over a contiguous row range.  A = A1 + t A2 when AXPY; B = A when
+// SAME.  Tiles of rows are staged in LDS with coalesced loads (the next tile is fetched into
+// registers while the current one is consumed); thread (rg, sub) owns the 4 x 4 sub-block `sub` of M
+// and accumulates the tile rows rg, rg + RG, ... in FP64.
 template <typename T, int K, bool AXPY, bool SAME>
 __global__ __launch_bounds__(kBlock) void gram_partial(int64_t n, int k, const T *__restrict__ A1, int64_t lda1,
                                                      const T *__restrict__ A2, int64_t lda2, double t,
@@ -27,7 +43,13 @@ __global__ __launch_bounds__(kBlock) void gram_partial(int64_t n, int k, const T
     constexpr int NS = K / 4;
     constexpr int TPR = NS * NS;
     constexpr int RG = kBlock / TPR;
-    __shared__ double s[kBlock][17];
+    constexpr int TR = gram_tile_rows<T, K>();
+    constexpr int KP = K + 4;  // padded LDS row (keeps 16-byte alignment of each 4-wide read)
+    constexpr int PER = TR * K / kBlock;  // tile values per thread per matrix
+    constexpr int NW = kBlock / 64;
+    __shared__ T sA[TR][KP];
+    __shared__ T sB[SAME ? 1 : TR][KP];
+    __shared__ double s_red[NW][TPR <= 64 ? TPR : 64][16];
     const int tid = threadIdx.x, sub = tid % TPR, rg = tid / TPR;
     const int a0 = (sub / NS) * 4, b0 = (sub % NS) * 4;
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -38,58 +60,102 @@ __global__ __launch_bounds__(kBlock) void gram_partial(int64_t n, int k, const T
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-    if (rg < RG) {
-        for (int64_t i = r0 + rg; i < r1; i += RG) {
+    T xa[PER], xb[PER];
+    auto fetch = [&](int64_t t0) {
+#pragma unroll
+        for (int v = 0; v < PER; ++v) {
+            const int e = tid + v * kBlock;
+            const int r = e / K, c = e % K;
+            const int64_t i = t0 + r;
+            T x = 0, y = 0;
+            if (i < r1 && c < k) {
+                x = A1[i * lda1 + c];
+                if (AXPY) x = (T)((double)x + t * (double)A2[i * lda2 + c]);
+                if (!SAME) y = B[i * ldb + c];
+            }
+            xa[v] = x;
+            xb[v] = y;
+        }
+    };
+    if (r0 < r1) fetch(r0);
+    for (int64_t t0 = r0; t0 < r1; t0 += TR) {
+#pragma unroll
+        for (int v = 0; v < PER; ++v) {
+            const int e = tid + v * kBlock;
+            sA[e / K][e % K] = xa[v];
+            if (!SAME) sB[e / K][e % K] = xb[v];
+        }
+        __syncthreads();
+        if (t0 + TR < r1) fetch(t0 + TR);
+        for (int r = rg; r < TR; r += RG) {
             double av[4], bv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int ca = a0 + q, cb = b0 + q;
-                double x = 0.0, y = 0.0;
-                if (ca < k) {
-                    x = (double)A1[i * lda1 + ca];
-                    if (AXPY) x += t * (double)A2[i * lda2 + ca];
-                }
-                if (cb < k) {
-                    if (SAME) {
-                        y = (double)A1[i * lda1 + cb];
-                        if (AXPY) y += t * (double)A2[i * lda2 + cb];
-                    } else {
-                        y = (double)B[i * ldb + cb];
-                    }
-                }
-                av[q] = x;
-                bv[q] = y;
+                av[q] = (double)sA[r][a0 + q];
+                bv[q] = SAME ? (double)sA[r][b0 + q] : (double)sB[r][b0 + q];
             }
 #pragma unroll
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) acc[p][q] = fma(av[p], bv[q], acc[p][q]);
         }
+        __syncthreads();
     }
+    // sum the row groups: inside a wave with shuffles, across waves in LDS, in a fixed order
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int o = TPR; o < 64; o <<= 1)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[tid][p * 4 + q] = acc[p][q];
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] += __shfl_xor(acc[p][q], o);
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane < (TPR <= 64 ? TPR : 64))
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_red[wave][lane][p * 4 + q] = acc[p][q];
     __syncthreads();
     if (tid < TPR) {
+        const int wl = TPR <= 64 ? tid : tid % 64;
         for (int e = 0; e < 16; ++e) {
             double v = 0.0;
-            for (int r = 0; r < RG; ++r) v += s[r * TPR + tid][e];
+            if (TPR <= 64) {  // every wave holds all TPR sub-blocks: add the waves in order
+                for (int w = 0; w < NW; ++w) v += s_red[w][wl][e];
+            } else {  // one row group: sub-block tid lives in wave tid / 64
+                v = s_red[tid / 64][wl][e];
+            }
             const int a = a0 + e / 4, b = b0 + e % 4;
             if (a < k && b < k) part[(int64_t)blockIdx.x * k * k + a * k + b] = v;
         }
     }
 }
 
-// Sum `nparts` partial arrays of `len` doubles in order.
-__global__ __launch_bounds__(kBlock) void sum_parts(const double *__restrict__ part, int nparts, int len,
+// One level of a fixed-order reduction: out[g][e] = sum_{q < kTreeFan} part[g*kTreeFan + q][e].
+__global__ __launch_bounds__(kBlock) void sum_level(const double *__restrict__ part, int nparts, int len,
                                                   double *__restrict__ out, double *__restrict__ out2) {
-    for (int e = threadIdx.x; e < len; e += kBlock) {
-        double v = 0.0;
-        for (int b = 0; b < nparts; ++b) v += part[(int64_t)b * len + e];
-        out[e] = v;
-        if (out2) out2[e] = v;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= len) return;
+    const int g = blockIdx.y;
+    const int q1 = (g + 1) * kTreeFan < nparts ? (g + 1) * kTreeFan : nparts;
+    double v[kTreeFan];
+#pragma unroll
+    for (int q = 0; q < kTreeFan; ++q) {
+        const int qq = g * kTreeFan + q;
+        v[q] = qq < q1 ? part[(int64_t)qq * len + e] : 0.0;
     }
+    double sacc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTreeFan; ++q) sacc += v[q];
+    out[(int64_t)g * len + e] = sacc;
+    if (out2) out2[(int64_t)g * len + e] = sacc;
+}
+
+// Sum kDenseBlocks partials of `len` doubles into out (and out2): two fixed-order levels.
+void sum_partials(const double *part, int len, double *mid, double *out, double *out2, hipStream_t s) {
+    constexpr int ngroups = kDenseBlocks / kTreeFan;
+    const unsigned gx = (unsigned)((len + kBlock - 1) / kBlock);
+    sum_level<<<dim3(gx, ngroups), kBlock, 0, s>>>(part, kDenseBlocks, len, mid, nullptr);
+    sum_level<<<dim3(gx, 1), kBlock, 0, s>>>(mid, ngroups, len, out, out2);
 }
 
 // Cholesky factor R (upper, positive diagonal) of the SPD k x k matrix M, and R^-1.  One workgroup;
@@ -126,43 +192,76 @@ __global__ __launch_bounds__(64) void chol_inv(int k, const double *__restrict__
     }
 }
 
-// out[i, :] = beta Z[i, :] + (A1[i, :] + t A2[i, :]) (s1 M1) + X[i, :] (s2 M2); one lane per row.
-template <typename T, int K, bool AXPY, bool HAS_X>
-__global__ __launch_bounds__(kBlock) void apply_rows(int64_t n, int k, double beta, const T *Z, int64_t ldz,
-                                                   const T *A1, int64_t lda1, const T *A2, int64_t lda2, double t,
-                                                   const double *__restrict__ M1, double s1, const T *X, int64_t ldx,
-                                                   const double *__restrict__ M2, double s2, T *out, int64_t ldo) {
-    __shared__ double sM1[K * K];
-    __shared__ double sM2[HAS_X ? K * K : 1];
-    for (int e = threadIdx.x; e < K * K; e += kBlock) {
+// out[i, :] = beta Z[i, :] + (A1[i, :] + t A2[i, :]) (s1 M1) + X[i, :] (s2 M2).
+// One lane per row: a tile of TR rows of each input is staged in LDS with coalesced loads, each lane
+// keeps its row's k outputs in FP64 registers, the k x k matrices are read with wave-uniform
+// addresses, and the outputs go back through LDS for a coalesced store.
+// Rows per apply tile: at most 256 (one lane each) and about 12 KB of LDS per staged matrix.
+template <typename T, int K>
+constexpr int apply_tile_rows() {
+    return (12288 / (K * (int)sizeof(T))) < 256 ? 12288 / (K * (int)sizeof(T)) : 256;
+}
+
+template <typename T, int K, bool AXPY, bool HAS_X, bool HAS_Z>
+__global__ __launch_bounds__(256) void apply_rows(int64_t n, int k, double beta, const T *Z, int64_t ldz,
+                                                const T *A1, int64_t lda1, const T *A2, int64_t lda2, double t,
+                                                const double *__restrict__ M1, double s1, const T *X, int64_t ldx,
+                                                const double *__restrict__ M2, double s2, T *out, int64_t ldo) {
+    constexpr int TR = apply_tile_rows<T, K>();
+    constexpr int KP = K + 1;
+    __shared__ T sA[TR][KP];
+    __shared__ T sX[HAS_X ? TR : 1][KP];
+    __shared__ T sZ[TR][KP];  // Z tile on the way in, the output tile on the way out
+    __shared__ double sM1[K][K];
+    __shared__ double sM2[HAS_X ? K : 1][K];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < K * K; e += TR) {
         const int a = e / K, c = e % K;
-        sM1[e] = (a < k && c < k) ? s1 * M1[a * k + c] : 0.0;
-        if (HAS_X) sM2[e] = (a < k && c < k) ? s2 * M2[a * k + c] : 0.0;
+        sM1[a][c] = (a < k && c < k) ? s1 * M1[a * k + c] : 0.0;
+        if (HAS_X) sM2[a][c] = (a < k && c < k) ? s2 * M2[a * k + c] : 0.0;
+    }
+    const int64_t t0 = (int64_t)blockIdx.x * TR;
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+        const int e = tid + v * TR;
+        const int r = e / K, c = e % K;
+        const int64_t i = t0 + r;
+        const bool ok = i < n && c < k;
+        T x = 0;
+        if (ok) {
+            x = A1[i * lda1 + c];
+            if (AXPY) x = (T)((double)x + t * (double)A2[i * lda2 + c]);
+        }
+        sA[r][c] = x;
+        if (HAS_X) sX[r][c] = ok ? X[i * ldx + c] : (T)0;
+        if (HAS_Z) sZ[r][c] = ok ? Z[i * ldz + c] : (T)0;
     }
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        double o[K];
+    double o[K];
 #pragma unroll
-        for (int c = 0; c < K; ++c) o[c] = (beta != 0.0 && c < k) ? beta * (double)Z[i * ldz + c] : 0.0;
-#pragma unroll 4
+    for (int c = 0; c < K; ++c) o[c] = HAS_Z ? beta * (double)sZ[tid][c] : 0.0;
+    for (int a = 0; a < k; ++a) {
+        const double av = (double)sA[tid][a];
+#pragma unroll
+        for (int c = 0; c < K; ++c) o[c] = fma(av, sM1[a][c], o[c]);
+    }
+    if (HAS_X) {
         for (int a = 0; a < k; ++a) {
-            double av = (double)A1[i * lda1 + a];
-            if (AXPY) av += t * (double)A2[i * lda2 + a];
+            const double xv = (double)sX[tid][a];
 #pragma unroll
-            for (int c = 0; c < K; ++c) o[c] = fma(av, sM1[a * K + c], o[c]);
+            for (int c = 0; c < K; ++c) o[c] = fma(xv, sM2[a][c], o[c]);
         }
-        if (HAS_X) {
-#pragma unroll 4
-            for (int a = 0; a < k; ++a) {
-                const double xv = (double)X[i * ldx + a];
+    }
+    __syncthreads();
 #pragma unroll
-                for (int c = 0; c < K; ++c) o[c] = fma(xv, sM2[a * K + c], o[c]);
-            }
-        }
+    for (int c = 0; c < K; ++c) sZ[tid][c] = (T)o[c];
+    __syncthreads();
 #pragma unroll
-        for (int c = 0; c < K; ++c)
-            if (c < k) out[i * ldo + c] = (T)o[c];
+    for (int v = 0; v < K; ++v) {
+        const int e = tid + v * TR;
+        const int r = e / K, c = e % K;
+        const int64_t i = t0 + r;
+        if (i < n && c < k) out[i * ldo + c] = sZ[r][c];
     }
 }
 
@@ -206,18 +305,23 @@ unsigned rows_grid(int64_t n, int per_block) {
     return (unsigned)g;
 }
 
+unsigned apply_grid(int64_t n, int tile) { return (unsigned)((n + tile - 1) / tile); }
+
 template <typename T, int K>
 pspec_status project_impl(int64_t n, int k, const T *U, int64_t ldu, const T *Z, int64_t ldz, const T *X, int64_t ldx,
                           const double *MX, T *out, int64_t ldo, double *M, double *ws, hipStream_t s) {
+    const size_t kk = (size_t)k * k;
     double *part = ws;
-    double *Mw = ws + (size_t)kDenseBlocks * k * k;
+    double *mid = part + kDenseBlocks * kk;
+    double *Mw = mid + (kDenseBlocks / kTreeFan) * kk;
+    constexpr int TR = apply_tile_rows<T, K>();
     gram_partial<T, K, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, Z, ldz, part);
-    sum_parts<<<1, kBlock, 0, s>>>(part, kDenseBlocks, k * k, Mw, M);
+    sum_partials(part, (int)kk, mid, Mw, M, s);
     if (X)
-        apply_rows<T, K, false, true><<<rows_grid(n, kBlock), kBlock, 0, s>>>(n, k, 1.0, Z, ldz, U, ldu, nullptr, 0,
-                                                                              0.0, Mw, -1.0, X, ldx, MX, -1.0, out, ldo);
+        apply_rows<T, K, false, true, true><<<apply_grid(n, TR), TR, 0, s>>>(n, k, 1.0, Z, ldz, U, ldu, nullptr, 0,
+                                                                             0.0, Mw, -1.0, X, ldx, MX, -1.0, out, ldo);
     else
-        apply_rows<T, K, false, false><<<rows_grid(n, kBlock), kBlock, 0, s>>>(
+        apply_rows<T, K, false, false, true><<<apply_grid(n, TR), TR, 0, s>>>(
             n, k, 1.0, Z, ldz, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr, 0, nullptr, 0.0, out, ldo);
     PSPEC_HIP(hipGetLastError());
     return PSPEC_OK;
@@ -226,13 +330,16 @@ pspec_status project_impl(int64_t n, int k, const T *U, int64_t ldu, const T *Z,
 template <typename T, int K>
 pspec_status retract_impl(int64_t n, int k, const T *U, int64_t ldu, const T *eta, int64_t lde, double t, T *out,
                           int64_t ldo, double *R, double *ws, hipStream_t s) {
+    const size_t kk = (size_t)k * k;
     double *part = ws;
-    double *Mw = ws + (size_t)kDenseBlocks * k * k;
-    double *Rinv = Mw + (size_t)k * k;
+    double *mid = part + kDenseBlocks * kk;
+    double *Mw = mid + (kDenseBlocks / kTreeFan) * kk;
+    double *Rinv = Mw + kk;
+    constexpr int TR = apply_tile_rows<T, K>();
     gram_partial<T, K, true, true><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, eta, lde, t, nullptr, 0, part);
-    sum_parts<<<1, kBlock, 0, s>>>(part, kDenseBlocks, k * k, Mw, nullptr);
+    sum_partials(part, (int)kk, mid, Mw, nullptr, s);
     chol_inv<<<1, 64, 0, s>>>(k, Mw, R, Rinv);
-    apply_rows<T, K, true, false><<<rows_grid(n, kBlock), kBlock, 0, s>>>(n, k, 0.0, U, ldu, U, ldu, eta, lde, t,
+    apply_rows<T, K, true, false, false><<<apply_grid(n, TR), TR, 0, s>>>(n, k, 0.0, nullptr, 0, U, ldu, eta, lde, t,
                                                                           Rinv, 1.0, nullptr, 0, nullptr, 0.0, out,
                                                                           ldo);
     PSPEC_HIP(hipGetLastError());
@@ -243,7 +350,7 @@ template <typename T, int K>
 pspec_status dot_impl(int64_t n, int k, const T *A, int64_t lda, const T *B, int64_t ldb, double *out, double *ws,
                       hipStream_t s) {
     dot_partial<T, K><<<kDenseBlocks, kBlock, 0, s>>>(n, k, A, lda, B, ldb, ws);
-    sum_parts<<<1, kBlock, 0, s>>>(ws, kDenseBlocks, 1, out, nullptr);
+    sum_partials(ws, 1, ws + kDenseBlocks, out, nullptr, s);
     PSPEC_HIP(hipGetLastError());
     return PSPEC_OK;
 }

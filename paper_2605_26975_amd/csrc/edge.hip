@@ -16,6 +16,8 @@
 //   G_i  = (p/D) (L_i - F phi_p(u_i))
 //   HV_i = (p/D) ((p-1) J_i - F (p-1) psi(u_i) v_i - G_i a - phi_p(u_i) b),  b = (p/D)(S - F a) = g^T v.
 #include <cmath>
+#include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 
@@ -104,11 +106,68 @@ __device__ __forceinline__ void write_partials(double q[kQ], double (*s_red)[kQ]
     }
 }
 
+// ---- cross-lane helpers (VALU only: DPP broadcasts, readlane, permlane swaps) ---------------
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Value of lane IDX of this lane's group of G lanes (G in {16, 32, 64}), for 32-bit payloads.
+template <int G, int IDX>
+__device__ __forceinline__ int32_t group_bcast(int32_t v, int lane) {
+    static_assert(IDX >= 0 && IDX < G, "lane index outside the group");
+    if constexpr (G == 16) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x150 + IDX, 0xf, 0xf, false);  // DPP row_newbcast
+    } else if constexpr (G == 32) {
+        const int32_t lo = __builtin_amdgcn_readlane(v, IDX);
+        const int32_t hi = __builtin_amdgcn_readlane(v, 32 + IDX);
+        return lane < 32 ? lo : hi;
+    } else {
+        return __builtin_amdgcn_readlane(v, IDX);
+    }
+}
+
+// Value of edge slot `e` at step U: lane U * EPR + e of the group (EPR edge slots per step).
+template <int G, int EPR, int U>
+__device__ __forceinline__ int32_t edge_bcast(int32_t v, int e, int lane) {
+    int32_t r = group_bcast<G, U * EPR>(v, lane);
+    static_for<1, EPR>([&](auto ec) {
+        constexpr int E = decltype(ec)::value;
+        const int32_t t = group_bcast<G, U * EPR + E>(v, lane);
+        r = e == E ? t : r;
+    });
+    return r;
+}
+
+template <typename T, int G, int EPR, int U>
+__device__ __forceinline__ T edge_bcast_val(T v, int e, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, edge_bcast<G, EPR, U>(__builtin_bit_cast(int32_t, v), e, lane));
+    } else {
+        const int64_t b = __builtin_bit_cast(int64_t, v);
+        const int32_t lo = edge_bcast<G, EPR, U>((int32_t)(b & 0xffffffff), e, lane);
+        const int32_t hi = edge_bcast<G, EPR, U>((int32_t)(b >> 32), e, lane);
+        return __builtin_bit_cast(T, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    }
+}
+
 // Light rows: a group of G lanes per row (K column lanes x G/K edge slots), kTileRows rows per
 // workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR ranges.
-template <typename T, typename WT, int K, int G, int MODE, int UNR>
+// A row is walked in chunks of G edges: the group loads the chunk's neighbour ids and weights with
+// one coalesced load (lane l of the group takes edge l), hands them to the lanes that need them with
+// VALU broadcasts (DPP row broadcast for 16-lane groups, readlane for 32- and 64-lane groups), and
+// issues every gather of the chunk before using any.  The ids of the group's next row are loaded
+// before the current row's gathers, so a row costs one memory latency, not two.  The gather rate of
+// random neighbour rows, not HBM bandwidth, bounds this kernel on random graphs: keeping 4 rows per
+// wave (16-lane groups for k <= 16) in flight matters more than the width of each load.
+
+template <typename T, typename WT, int K, int G, int MODE>
 __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
-    constexpr int EPR = G / K;
+    constexpr int EPR = G / K;   // edge slots per row
+    constexpr int NU = G / EPR;  // shuffle steps per chunk of G edges (= K)
     constexpr int NGRP = kBlock / G;
     constexpr int RS = kTileRows / NGRP;
     static_assert(kTileRows % NGRP == 0, "tile rows must split evenly over groups");
@@ -116,7 +175,9 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
     __shared__ double s_red[kBlock / 64][kQ][K];
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int grp = tid / G, gl = tid % G;
+    const int gbase = lane - gl;  // first lane of this group within the wave
     const int c = gl % K, e = gl / K;
     const int cl = c < a.k ? c : a.k - 1;
     const uint32_t cb = (uint32_t)cl * (uint32_t)sizeof(T);
@@ -129,48 +190,78 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
 
     const auto rU = make_rsrc(a.U, a.U_bytes);
     const auto rV = make_rsrc(a.V, a.V_bytes);
+    // ids and weights of the first chunk of local row rl (padding: the row itself, weight 0)
+    auto first_chunk = [&](int rl, int32_t &jl, T &wl) {
+        const int64_t row = row0 + rl;
+        jl = row < a.n ? (int32_t)row : 0;
+        wl = (T)0;
+        if (row < a.n) {
+            const int64_t b = s_rp[rl], d = s_rp[rl + 1] - b;
+            if (d <= a.light_max && gl < d) {
+                jl = a.col[b + gl];
+                wl = (T)a.w[b + gl];
+            }
+        }
+    };
+    int32_t jl;
+    T wl;
+    first_chunk(grp, jl, wl);
     double q[kQ] = {0.0, 0.0, 0.0, 0.0};  // N, D, a, S
     for (int s = 0; s < RS; ++s) {
         const int rl = grp + s * NGRP;
         const int64_t row = row0 + rl;
-        if (row >= a.n) break;
-        const int64_t beg = s_rp[rl], end = s_rp[rl + 1];
-        const T ui = bload<T>(rU, (uint32_t)row * a.ldu_b + cb);
+        const bool valid = row < a.n;
+        const int64_t beg = valid ? s_rp[rl] : 0, end = valid ? s_rp[rl + 1] : 0;
+        const bool light = valid && (end - beg) <= a.light_max;
+        const int64_t len = light ? end - beg : 0;
+        const uint32_t own = valid ? (uint32_t)row : 0u;
+        const T ui = bload<T>(rU, own * a.ldu_b + cb);
         T vi = 0;
-        if (MODE == HVP) vi = bload<T>(rV, (uint32_t)row * a.ldv_b + cb);
+        if (MODE == HVP) vi = bload<T>(rV, own * a.ldv_b + cb);
+        int32_t jn = 0;
+        T wn = (T)0;
+        if (s + 1 < RS) first_chunk(rl + NGRP, jn, wn);  // prefetch the next row's ids
+        const int nch = (int)((len + G - 1) / G);
         T Ls = 0, Js = 0, Ns = 0;
-        const bool light = (end - beg) <= a.light_max;
-        if (light) {
-            for (int64_t base = beg; base < end; base += EPR * UNR) {
-                int32_t j[UNR];
-                T wv[UNR];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    const int64_t idx = base + u * EPR + e;
-                    const bool ok = idx < end;
-                    j[u] = ok ? a.col[idx] : (int32_t)row;
-                    wv[u] = ok ? (T)a.w[idx] : (T)0;
-                }
-                T uj[UNR], vj[UNR];
-#pragma unroll
-                for (int u = 0; u < UNR; ++u) {
-                    uj[u] = bload<T>(rU, (uint32_t)j[u] * a.ldu_b + cb);
-                    vj[u] = (MODE == HVP) ? bload<T>(rV, (uint32_t)j[u] * a.ldv_b + cb) : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < UNR; ++u)
-                    Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wv[u], Ls, Js, Ns);
+        for (int ch = 0; ch < nch; ++ch) {
+            const int64_t c0 = beg + (int64_t)ch * G;
+            const int64_t rem = len - (int64_t)ch * G;
+            const int cnt = rem <= 0 ? 0 : (rem < G ? (int)rem : G);
+            if (ch > 0) {
+                jl = gl < cnt ? a.col[c0 + gl] : (int32_t)own;
+                wl = gl < cnt ? (T)a.w[c0 + gl] : (T)0;
             }
-            if (EPR > 1) {
-#pragma unroll
-                for (int o = K; o < G; o <<= 1) {
-                    if (MODE != OBJ) Ls += __shfl_xor(Ls, o);
-                    if (MODE == HVP) Js += __shfl_xor(Js, o);
+            T uj[NU], vj[NU];
+            static_for<0, NU>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                uj[u] = ui;
+                vj[u] = vi;
+                if (u * EPR < cnt) {
+                    const int32_t j = edge_bcast<G, EPR, u>(jl, e, lane);
+                    uj[u] = bload<T>(rU, (uint32_t)j * a.ldu_b + cb);
+                    if (MODE == HVP) vj[u] = bload<T>(rV, (uint32_t)j * a.ldv_b + cb);
                 }
+            });
+            // every gather of the chunk is in flight before the first one is used
+            static_for<0, NU>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                if (u * EPR < cnt) {
+                    const T wv = edge_bcast_val<T, G, EPR, u>(wl, e, lane);
+                    Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wv, Ls, Js, Ns);
+                }
+            });
+        }
+        jl = jn;
+        wl = wn;
+        if (EPR > 1) {
+#pragma unroll
+            for (int o = K; o < G; o <<= 1) {
+                if (MODE != OBJ) Ls += __shfl_xor(Ls, o);
+                if (MODE == HVP) Js += __shfl_xor(Js, o);
             }
         }
         q[0] += (double)Ns;
-        if (e == 0) {
+        if (valid && e == 0) {
             const T hi = a.pw(fabs(ui));
             const T phi = hi * ui;  // phi_p(u_i)
             q[1] += (double)(phi * ui);
@@ -400,11 +491,13 @@ pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, 
     a.scratch = g->chunk_scratch;
     a.k_max = g->k_max;
     a.part_base = g->tiles;
-    edge_light<T, WT, K, light_group<K>(), MODE, kUnroll><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
+    if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
+    edge_light<T, WT, K, light_group<K>(), MODE><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     if (g->n_chunks > 0) edge_heavy<T, WT, K, MODE, kUnroll><<<(unsigned)g->n_chunks, kBlock, 0, s>>>(a);
     if (g->n_split > 0 && MODE != OBJ)
         combine_split<T, MODE><<<grid_for(g->n_split * k, kBlock, 1 << 30), kBlock, 0, s>>>(
             g->splits, g->n_split, g->chunk_scratch, k, g->k_max, L, ldl, J, ldj);
+    if (g->ev_after) PSPEC_HIP(hipEventRecord(g->ev_after, s));
     const int W = kQ * k;
     reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + g->n_chunks, W, g->red1);
     reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F);

@@ -318,3 +318,12 @@ extern "C" pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int
     if (split_rows) *split_rows = g->n_split;
     return PSPEC_OK;
 }
+
+extern "C" pspec_status pspec_graph_set_timing_events(pspec_graph g, pspec_event before, pspec_event after) {
+    clear_error();
+    PSPEC_ARG(g != nullptr, "graph_set_timing_events: NULL handle");
+    PSPEC_ARG((before == nullptr) == (after == nullptr), "graph_set_timing_events: give both events or neither");
+    g->ev_before = reinterpret_cast<hipEvent_t>(before);
+    g->ev_after = reinterpret_cast<hipEvent_t>(after);
+    return PSPEC_OK;
+}

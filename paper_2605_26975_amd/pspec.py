@@ -12,7 +12,8 @@ import os
 
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpspec.so")
+# The in-tree build; PSPEC_LIBRARY may name another build of the same C ABI.
+LIB_PATH = os.environ.get("PSPEC_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpspec.so")
 
 PSPEC_F32, PSPEC_F64 = 0, 1
 _STATUS = {0: "PSPEC_OK", 1: "PSPEC_ERR_ARG", 2: "PSPEC_ERR_UNSUPPORTED", 3: "PSPEC_ERR_HIP", 4: "PSPEC_ERR_WORKSPACE"}
@@ -42,6 +43,7 @@ def lib() -> ctypes.CDLL:
         "pspec_graph_create": [i64, i64, vp, vp, vp, i32, i32, vp, ctypes.POINTER(vp)],
         "pspec_graph_destroy": [vp],
         "pspec_graph_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "pspec_graph_set_timing_events": [vp, vp, vp],
         "pspec_objective": [vp, i32, i32, vp, i64, dbl, vp, vp, vp],
         "pspec_grad": [vp, i32, i32, vp, i64, dbl, vp, i64, vp, vp],
         "pspec_hvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp],
@@ -65,7 +67,8 @@ def lib() -> ctypes.CDLL:
 def exported_symbols() -> list[str]:
     """Names of the entry points the binding declares (all must resolve in the library)."""
     return [
-        "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info", "pspec_objective", "pspec_grad",
+        "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info", "pspec_graph_set_timing_events",
+        "pspec_objective", "pspec_grad",
         "pspec_hvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
         "pspec_axpby", "pspec_last_error",
     ]
@@ -151,6 +154,10 @@ class Graph:
         h, c, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().pspec_graph_info(self.handle, ctypes.byref(h), ctypes.byref(c), ctypes.byref(s)))
         return dict(heavy_rows=h.value, chunks=c.value, split_rows=s.value)
+
+    def set_timing_events_raw(self, before, after) -> None:
+        """Record two raw hipEvent_t handles (or None, None) around the edge pass of later calls."""
+        _check(lib().pspec_graph_set_timing_events(self.handle, before, after))
 
     def close(self) -> None:
         if self._h:

@@ -33,9 +33,17 @@ def device_graph(g, k_max, weight_dtype=torch.float32):
     return pspec.Graph.from_host(g, "cuda", k_max=k_max, weight_dtype=weight_dtype)
 
 
-def gpu_hvp(dg, U, V, p, eps, dtype):
-    Ut = torch.as_tensor(U).to(dtype).cuda()
-    Vt = torch.as_tensor(V).to(dtype).cuda()
+def gpu_hvp(dg, U, V, p, eps, dtype, layout="separate"):
+    """layout: "separate" (two n x k arrays) or "interleaved" (halves of one n x 2k array)."""
+    if layout == "interleaved":
+        k = U.shape[1]
+        P = torch.empty((U.shape[0], 2 * k), dtype=dtype, device="cuda")
+        P[:, :k] = torch.as_tensor(U).to(dtype)
+        P[:, k:] = torch.as_tensor(V).to(dtype)
+        Ut, Vt = P[:, :k], P[:, k:]
+    else:
+        Ut = torch.as_tensor(U).to(dtype).cuda()
+        Vt = torch.as_tensor(V).to(dtype).cuda()
     HV, G, Fc = pspec.hvp(dg, Ut, Vt, p, eps)
     torch.cuda.synchronize()
     return HV.double().cpu().numpy(), G.double().cpu().numpy(), Fc.cpu().numpy()
@@ -53,13 +61,13 @@ def oracle_hvp(g, U, V, p, eps):
     return o.hvp(g.rowptr, g.col, g.w.astype(np.float64), U.astype(np.float64), V.astype(np.float64), p, eps)
 
 
-def compare(g, k, p, eps, dtype, U=None, V=None, dg=None):
+def compare(g, k, p, eps, dtype, U=None, V=None, dg=None, layout="separate"):
     """Errors of the GPU path against the oracle: dict with F, Fcol (max rel), G, HV (Frobenius rel)."""
     if U is None:
         U, V = inputs(g.n, k)
     if dg is None:
         dg = device_graph(g, k)
-    HVg, Gg, Fcg = gpu_hvp(dg, U, V, p, eps, dtype)
+    HVg, Gg, Fcg = gpu_hvp(dg, U, V, p, eps, dtype, layout)
     HVo, Go, Fco = oracle_hvp(g, U, V, p, eps)
     Fg, Fcg2 = gpu_objective(dg, U, p, dtype)
     err = dict(

@@ -46,13 +46,15 @@ def test_sbm1000_fp32_fused_path(sbm1000, p):
     assert e["HV"] < F32_TOL_HV, e
 
 
-@pytest.mark.parametrize("k", [1, 3, 16, 33])
-def test_multitile_ragged(k):
-    """50,000 nodes (195 full tiles and a ragged one), k from 1 to 33 (padded column lanes)."""
-    print(f"[case] sbm50k k={k}", flush=True)
+@pytest.mark.parametrize("k", [1, 3, 8, 13, 16, 32, 33])
+@pytest.mark.parametrize("layout", ["separate", "interleaved"])
+def test_multitile_ragged(k, layout):
+    """50,000 nodes (195 full tiles and a ragged one), k from 1 to 33 (padded column lanes), U and V
+    as separate arrays or as the two halves of one n x 2k array."""
+    print(f"[case] sbm50k k={k} {layout}", flush=True)
     g = gen.sbm_edges(50_000, 16, 270_000, 30_000, 0.5, 1.5, seed=7)
     for dtype, tol in ((torch.float32, F32_TOL_G), (torch.float64, F64_TOL)):
-        e = gu.compare(g, k, 1.3, 1e-8, dtype)
+        e = gu.compare(g, k, 1.3, 1e-8, dtype, layout=layout)
         assert e["F"] < tol and e["G"] < tol, (dtype, e)
         assert e["HV"] < (F32_TOL_HV if dtype == torch.float32 else F64_TOL), (dtype, e)
 
@@ -91,11 +93,12 @@ def test_heavy_and_split_rows(k):
         assert e["HV"] < (F32_TOL_HV if dtype == torch.float32 else F64_TOL), (dtype, e)
 
 
-def test_rmat_scale14_p105():
+@pytest.mark.parametrize("layout", ["separate", "interleaved"])
+def test_rmat_scale14_p105(layout):
     """Skewed degrees (R-MAT), k = 32, p = 1.05, eps = 1e-8."""
-    print("[case] rmat14", flush=True)
+    print(f"[case] rmat14 {layout}", flush=True)
     g = gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9)
-    e32 = gu.compare(g, 32, 1.05, 1e-8, torch.float32)
+    e32 = gu.compare(g, 32, 1.05, 1e-8, torch.float32, layout=layout)
     print(e32)
     assert e32["F"] < F32_TOL_F and e32["G"] < F32_TOL_G and e32["HV"] < F32_TOL_HV, e32
     e64 = gu.compare(g, 32, 1.05, 1e-8, torch.float64)
