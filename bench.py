@@ -32,7 +32,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "p-Laplacian grad+HVP edge·col updates/s, FP32 vs FP64, % HBM peak"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_hvp_sbm8m_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "edge_hvp_sbm8m_traffic.json")
+EDGE_KERNEL = "edge_light<float, float, 16, 16, 2>"  # the fused grad+HVP edge pass at k = 16
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
 
 
 def edge_source_hash() -> str:
@@ -94,6 +97,85 @@ class HipEvents:
             self.hip.hipEventDestroy(b)
 
 
+def _csv_rows(pattern):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(pattern, recursive=True)):
+        with open(f) as fh:
+            rows.extend({k.lower(): v for k, v in r.items()} for r in csv.DictReader(fh))
+    return rows
+
+
+def summarize_profile(trace_dir: str, fetch_dir: str, write_dir: str, cmd_trace: str, cmd_fetch: str,
+                      cmd_write: str) -> None:
+    """Write the committed profile summaries from rocprofv3 CSV output (kernel stats and the
+    FETCH_SIZE / WRITE_SIZE counter runs)."""
+    import statistics
+
+    stats = _csv_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    lines = ["# Kernel trace: SBM n=8,000,000, k=16, p=1.1, FP32, interleaved U|V", "",
+             "Command (from the repository root, on one MI355X):", "", "```", cmd_trace, "```", "",
+             "| kernel | calls | average us | share % |", "|---|---|---|---|"]
+    for r in stats[:14]:
+        name = r["name"].replace("pspec::(anonymous namespace)::", "")
+        name = name.split("(")[0][:80]
+        lines.append(f"| `{name}` | {r['calls']} | {float(r['averagens']) / 1e3:.1f} | {float(r['percentage']):.1f} |")
+    with open(os.path.join(PROFILES, "edge_hvp_sbm8m_kernel_trace.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def per_dispatch(rows, counter, pred):
+        vals = [float(r["counter_value"]) for r in rows if r["counter_name"] == counter and pred(r["kernel_name"])]
+        return statistics.median(vals) if vals else None
+
+    fetch = _csv_rows(os.path.join(fetch_dir, "**", "*counter_collection.csv"))
+    write = _csv_rows(os.path.join(write_dir, "**", "*counter_collection.csv"))
+    is_edge = lambda nm: EDGE_KERNEL in nm.replace("pspec::(anonymous namespace)::", "")  # noqa: E731
+    is_copy = lambda nm: "axpby_k<float, 16>" in nm  # the calibration copy (bench.py --copy-calibration)
+    f_edge = per_dispatch(fetch, "FETCH_SIZE", is_edge)
+    w_edge = per_dispatch(write, "WRITE_SIZE", is_edge)
+    f_copy = per_dispatch(fetch, "FETCH_SIZE", is_copy)
+    w_copy = per_dispatch(write, "WRITE_SIZE", is_copy)
+    kib = COPY_BYTES / 1024.0
+    f_scale = kib / f_copy if f_copy else None
+    w_scale = kib / w_copy if w_copy else None
+    traffic = None
+    if f_edge is not None and w_edge is not None and f_scale and w_scale:
+        traffic = (f_edge * f_scale + w_edge * w_scale) * 1024.0
+    out = {
+        "workload": "sbm8m",
+        "layout": "interleaved",
+        "kernel": EDGE_KERNEL,
+        "source_hash": edge_source_hash(),
+        "fetch_kib_per_dispatch": f_edge,
+        "write_kib_per_dispatch": w_edge,
+        "copy_fetch_kib": f_copy,
+        "copy_write_kib": w_copy,
+        "fetch_scale": f_scale,
+        "write_scale": w_scale,
+        "bytes_per_launch": traffic,
+        "commands": [cmd_fetch, cmd_write],
+    }
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    alg = None
+    md = ["# HBM traffic of the fused grad+HVP edge pass: SBM n=8,000,000, k=16, FP32", "",
+          "Counter runs (from the repository root, one MI355X, one counter block per run):", "", "```",
+          cmd_fetch, cmd_write, "```", "",
+          f"A plain device copy of {COPY_BYTES >> 20} MiB (read and written once) calibrates each counter: "
+          f"scale = known KiB / counted KiB.", "",
+          "| quantity | value |", "|---|---|",
+          f"| FETCH_SIZE, edge kernel (KiB/dispatch, median) | {f_edge} |",
+          f"| WRITE_SIZE, edge kernel (KiB/dispatch, median) | {w_edge} |",
+          f"| FETCH_SIZE, copy (KiB) | {f_copy} |", f"| WRITE_SIZE, copy (KiB) | {w_copy} |",
+          f"| fetch scale | {f_scale} |", f"| write scale | {w_scale} |",
+          f"| HBM bytes per launch (scaled) | {traffic} |"]
+    with open(os.path.join(PROFILES, "edge_hvp_sbm8m_traffic.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    del alg
+
+
 def cpu_baseline(args):
     """Time the FP64 oracle (as it stands) on a quarter-scale sample of the same workload."""
     import numpy as np
@@ -129,7 +211,15 @@ def main() -> int:
                     help="U and V as the two halves of one n x 2k array, or two n x k arrays")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration for profiles)")
+    ap.add_argument("--summarize-profile", nargs=6, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_TRACE",
+                                                            "CMD_FETCH", "CMD_WRITE"),
+                    help="write the profiles/ summaries from rocprofv3 CSV output and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(*args.summarize_profile)
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}, "
@@ -211,6 +301,14 @@ def main() -> int:
         ok = bool(torch.isfinite(F).item()) and bool(torch.isfinite(HV).all().item())
         return total_ms / steps, edge_ms, ok
 
+    if args.copy_calibration:
+        # Y <- 1 * X + 0 * Y through the library's axpby: reads X once, writes Y once (a plain copy)
+        src = torch.ones((COPY_BYTES // 64, 16), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            pspec.axpby(1.0, src, 0.0, dst)
+        torch.cuda.synchronize()
+        del src, dst
     t32, edge32, ok32 = run(torch.float32, args.steps, args.warmup)
     print(f"[bench] fp32 step {t32:.3f} ms, edge pass {np.mean(edge32):.3f} ms", file=sys.stderr, flush=True)
     fp64 = None
