@@ -1,0 +1,129 @@
+"""GPU: the torch.autograd.Function wrappers (checked against central finite differences and the
+FP64 oracle gradient) and the Newton-tCG clustering driver."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_26975_amd import autograd as pag
+from paper_2605_26975_amd import driver, gen, pspec
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def grid128():
+    """The 3-D 6-neighbour 128^3 grid (2,097,152 nodes), k = 8, p = 1.2."""
+    return gen.grid3d(128)
+
+
+def _away_from_kinks(g, U, V, delta=1e-2):
+    """V with zeros wherever a central difference along V could cross a kink of |x|^(p-1) or
+    |u|^(p-1): at both ends of every edge with |u_i - u_j| < delta and where |u_i| < delta, per
+    column.  With |h V| <= 1e-5 the differences then stay >= 1e3 |h (v_i - v_j)| from every kink.
+    Returns the masked V and the number of zeroed entries."""
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    near = np.abs(U[rows] - U[g.col]) < delta
+    zero = np.abs(U) < delta
+    np.logical_or.at(zero, rows, near)
+    Vm = np.where(zero, 0.0, V).astype(V.dtype)
+    return Vm, int(zero.sum())
+
+
+def test_autograd_gradient_vs_oracle_and_fd(grid128):
+    g = grid128
+    k, p, eps, h = 8, 1.2, 1e-8, 1e-6
+    print(f"[case] grid128 autograd k={k} p={p}", flush=True)
+    U, V = gu.inputs(g.n, k)
+    dg = gu.device_graph(g, k)
+    # FP32 autograd gradient against the FP64 oracle gradient
+    U32 = torch.as_tensor(U).cuda().requires_grad_(True)
+    F32 = pag.objective(U32, dg, p, eps)
+    (G32,) = torch.autograd.grad(F32, U32)
+    _, Go, Fco = gu.oracle_hvp(g, U, V, p, eps)
+    assert gu.rel(G32.double().cpu().numpy(), Go) < 1e-5
+    assert abs(float(F32) - Fco.sum()) / Fco.sum() < 1e-5
+    # FP64 path: directional derivative against a central difference of F
+    Vm, zeroed = _away_from_kinks(g, U, V)
+    print(f"direction zeroed at {zeroed} of {V.size} entries near kinks")
+    assert zeroed < 0.05 * V.size
+    U64 = torch.as_tensor(U).double().cuda().requires_grad_(True)
+    V64 = torch.as_tensor(Vm).double().cuda()
+    F64 = pag.objective(U64, dg, p, eps)
+    (G64,) = torch.autograd.grad(F64, U64, create_graph=True)
+    with torch.no_grad():
+        Fp = float(pag.objective(U64 + h * V64, dg, p, eps))
+        Fm = float(pag.objective(U64 - h * V64, dg, p, eps))
+    fd = (Fp - Fm) / (2 * h)
+    an = float((G64 * V64).sum())
+    assert abs(an - fd) <= 1e-6 * abs(fd), (an, fd)
+
+
+def test_autograd_hvp_vs_fd_and_forward_mode(grid128):
+    g = grid128
+    k, p, eps, h = 8, 1.2, 1e-8, 1e-6
+    print(f"[case] grid128 hvp fd k={k} p={p}", flush=True)
+    U, V = gu.inputs(g.n, k)
+    dg = gu.device_graph(g, k)
+    Vm, zeroed = _away_from_kinks(g, U, V)
+    print(f"direction zeroed at {zeroed} of {V.size} entries near kinks")
+    U64 = torch.as_tensor(U).double().cuda().requires_grad_(True)
+    V64 = torch.as_tensor(Vm).double().cuda()
+    # reverse-over-reverse: d/dU <G(U), V> = H V
+    F = pag.objective(U64, dg, p, eps)
+    (G,) = torch.autograd.grad(F, U64, create_graph=True)
+    (HV_rr,) = torch.autograd.grad(G, U64, grad_outputs=V64)
+    # forward-over-reverse: forward-mode derivative of the gradient along V
+    import torch.autograd.forward_ad as fwAD
+
+    with fwAD.dual_level():
+        G_dual = pag.gradient(fwAD.make_dual(U64.detach(), V64), dg, p, eps)
+        HV_fr = fwAD.unpack_dual(G_dual).tangent
+    assert torch.equal(HV_rr, HV_fr)
+    # central difference of the gradient, row by row away from the kinks of |x|^(p-1)
+    with torch.no_grad():
+        Gp = pag.gradient(U64 + h * V64, dg, p, eps)
+        Gm = pag.gradient(U64 - h * V64, dg, p, eps)
+    fd = ((Gp - Gm) / (2 * h)).cpu().numpy()
+    hv = HV_rr.cpu().numpy()
+    err = np.linalg.norm(hv - fd) / np.linalg.norm(fd)
+    print(f"HVP vs central difference of the gradient: {err:.2e}")
+    assert err < 1e-5, err
+    # the FP32 HVP kernel against the FP64 oracle on the same inputs
+    HVo, _, _ = gu.oracle_hvp(g, U, V, p, eps)
+    HV32, _, _ = gu.gpu_hvp(dg, U, V, p, eps, torch.float32)
+    assert gu.rel(HV32, HVo) < 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_cluster_sbm1000_recovers_blocks(dtype):
+    g = gen.sbm_bernoulli(1000, 4, 0.05, 0.002)
+    truth = np.repeat(np.arange(4), 250)
+    dg = gu.device_graph(g, 4)
+    for p in (2.0, 1.3):
+        print(f"[case] cluster sbm1000 {dtype} p={p}", flush=True)
+        labels, U, infos, rc = driver.cluster(dg, g, 4, p, dtype=dtype)
+        acc = driver.matched_accuracy(labels, truth)
+        print(f"p={p} accuracy={acc:.4f} RCut={rc:.5f} newton={[i.iterations for i in infos]}")
+        assert acc >= 0.95
+        Uh = U.double().cpu().numpy()
+        assert np.max(np.abs(Uh.T @ Uh - np.eye(4))) < (1e-5 if dtype == torch.float32 else 1e-12)
+
+
+def test_cluster_knn_fp32_matches_fp64():
+    """kNN mixture (100k points, k = 8, p = 1.3): FP32 and FP64 labels agree.  With
+    w = exp(-d^2 / s^2) and s ~ 0.056 many tail points have weights that round to 0 in FP32, so the
+    minimiser isolates them (RCut ~ 2e-4) and labels do not follow the mixture components; the
+    comparison is FP32 against FP64."""
+    g = gen.knn_mixture(100_000, 8, 10, 1.0, 20.0)
+    truth = g.meta["labels"]
+    dg = gu.device_graph(g, 8)
+    out = {}
+    for dtype in (torch.float32, torch.float64):
+        print(f"[case] cluster knn100k {dtype}", flush=True)
+        labels, U, infos, rc = driver.cluster(dg, g, 8, 1.3, dtype=dtype)
+        out[dtype] = labels
+        print(f"{dtype}: accuracy vs mixture {driver.matched_accuracy(labels, truth):.4f} RCut {rc:.5f}")
+    agree = driver.matched_accuracy(out[torch.float32], out[torch.float64])
+    print(f"FP32 vs FP64 label agreement {agree:.5f}")
+    assert agree >= 0.99
