@@ -1,0 +1,40 @@
+"""GPU parity at the full sizes of the five workloads, in the benchmark's launch configuration
+(U and V as the two halves of one n x 2k array), against the FP64 oracle on every output.
+
+Each case generates its graph, runs the oracle over all edges (multi-threaded; tens of seconds
+for the largest) and compares F (relative), G and HV (relative Frobenius over the block) for the
+FP32 fused path and the FP64 plain path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_26975_amd import gen
+from tests import gpu_util as gu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.mark.parametrize("name", ["knn100k", "grid128", "sbm8m", "rmat22"])
+def test_fullsize_vs_oracle(name):
+    cfg = gen.CONFIGS[name]
+    k, p, eps = cfg["k"], cfg["p"][0], cfg["eps"]
+    print(f"[case] fullsize {name} k={k} p={p}: generating", flush=True)
+    g = cfg["graph"]()
+    U, V = gu.inputs(g.n, k)
+    dg = gu.device_graph(g, k)
+    info = dg.info()
+    print(f"[case] fullsize {name}: n={g.n} nnz={g.nnz} schedule={info}; oracle", flush=True)
+    HVo, Go, Fco = gu.oracle_hvp(g, U, V, p, eps)
+    for dtype, tol_fg, tol_hv in ((torch.float32, 1e-5, 1e-4), (torch.float64, 1e-11, 1e-11)):
+        print(f"[case] fullsize {name}: {dtype}", flush=True)
+        HV, G, Fc = gu.gpu_hvp(dg, U, V, p, eps, dtype, layout="interleaved")
+        eF = float(np.max(np.abs(Fc - Fco) / np.abs(Fco)))
+        eG, eH = gu.rel(G, Go), gu.rel(HV, HVo)
+        print(f"{name} {dtype}: F {eF:.2e}  G {eG:.2e}  HV {eH:.2e}", flush=True)
+        assert eF < tol_fg and eG < tol_fg and eH < tol_hv, (eF, eG, eH)
+        del HV, G
+    if name == "rmat22":
+        assert info["heavy_rows"] > 0 and info["split_rows"] > 0
+        HV, G, Fc = gu.gpu_hvp(dg, U, V, p, eps, torch.float32, layout="separate")
+        assert gu.rel(G, Go) < 1e-5 and gu.rel(HV, HVo) < 1e-4
