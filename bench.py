@@ -34,8 +34,15 @@ METRIC = "p-Laplacian grad+HVP edge·col updates/s, FP32 vs FP64, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "edge_hvp_sbm8m_traffic.json")
-EDGE_KERNEL = "edge_light<float, float, 16, 16, 2>"  # the fused grad+HVP edge pass at k = 16
+EDGE_KERNEL = "edge_light<float, float, 16, 2>"  # the fused grad+HVP edge pass at k = 16
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
+WORKLOADS = {
+    "sbm8m": "sbm8m: SBM n=8,000,000, 16 blocks, mean degree 12, w~U[0.5,1.5], k=16, p=1.1, eps=1e-8",
+    "rmat22": "rmat22: R-MAT scale 22, edge factor 16, (0.57,0.19,0.19), w~U[0.1,1], k=32, p=1.05, eps=1e-8",
+    "grid128": "grid128: 3-D 6-neighbour grid 128^3, unit weights, k=8, p=1.2, eps=1e-8",
+    "knn100k": "knn100k: 10-NN of a 2-D 8-component Gaussian mixture, 100k points, k=8, p=1.3, eps=1e-8",
+    "sbm1000": "sbm1000: SBM n=1000, 4 blocks, p_in 0.05, p_out 0.002, k=4, p=1.1, eps=1e-8",
+}
 
 
 def edge_source_hash() -> str:
@@ -132,7 +139,7 @@ def summarize_profile(trace_dir: str, fetch_dir: str, write_dir: str, cmd_trace:
     fetch = _csv_rows(os.path.join(fetch_dir, "**", "*counter_collection.csv"))
     write = _csv_rows(os.path.join(write_dir, "**", "*counter_collection.csv"))
     is_edge = lambda nm: EDGE_KERNEL in nm.replace("pspec::(anonymous namespace)::", "")  # noqa: E731
-    is_copy = lambda nm: "axpby_k<float, 16>" in nm  # the calibration copy (bench.py --copy-calibration)
+    is_copy = lambda nm: "axpby_k<float, 16, true>" in nm  # the calibration copy (bench.py --copy-calibration)
     f_edge = per_dispatch(fetch, "FETCH_SIZE", is_edge)
     w_edge = per_dispatch(write, "WRITE_SIZE", is_edge)
     f_copy = per_dispatch(fetch, "FETCH_SIZE", is_copy)
@@ -207,8 +214,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sbm8m", choices=["sbm8m", "rmat22", "grid128", "knn100k", "sbm1000"],
+                    help="the headline is sbm8m; the others are reported for load balance and context")
     ap.add_argument("--layout", default="interleaved", choices=["interleaved", "separate"],
                     help="U and V as the two halves of one n x 2k array, or two n x k arrays")
+    ap.add_argument("--step", default="fused", choices=["fused", "unfused"],
+                    help="fused: one pspec_rhvp call for the Riemannian gradient and Hessian; unfused: pspec_hvp "
+                         "and two pspec_project calls (identical results)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -234,8 +246,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = gen.CONFIGS["sbm8m"]
-    k, p, eps = cfg["k"], cfg["p"][0], cfg["eps"]
+    cfg = gen.CONFIGS[args.workload]
+    k, p, eps = cfg["k"], cfg["p"][-1], cfg["eps"]
     t0 = time.perf_counter()
     g = cfg["graph"]()
     print(f"[bench] graph n={g.n} nnz={g.nnz} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
@@ -258,8 +270,9 @@ def main() -> int:
 
     def run(dtype, steps, warmup, timed_kernel=True):
         U, V, keep = make_inputs(dtype)
-        HV = torch.empty((n, k), dtype=dtype, device=dev)
-        G = torch.empty((n, k), dtype=dtype, device=dev)
+        unfused = args.step != "fused"
+        HV = torch.empty((n, k), dtype=dtype, device=dev) if unfused else None
+        G = torch.empty((n, k), dtype=dtype, device=dev) if unfused else None
         RG = torch.empty((n, k), dtype=dtype, device=dev)
         RH = torch.empty((n, k), dtype=dtype, device=dev)
         Un = torch.empty((n, k), dtype=dtype, device=dev)
@@ -269,10 +282,20 @@ def main() -> int:
         Fc2 = torch.empty(k, dtype=torch.float64, device=dev)
         t_step = -1e-3
 
-        def step():
-            pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc)
-            pspec.project(U, G, out=RG, M=MG)
-            pspec.project(U, HV, X=V, MX=MG, out=RH)
+        def step(pair=None):
+            # Riemannian gradient and Hessian applied to V (edge pass, epilogue, Gram matrices and
+            # projections), a retraction along the Riemannian gradient, the objective there
+            if pair is not None:
+                dg.set_timing_events_raw(*pair)
+            if args.step == "fused":
+                pspec.rhvp(dg, U, V, p, eps, RH=RH, RG=RG, MG=MG, F_col=Fc)
+            else:
+                pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc)
+            if pair is not None:
+                dg.set_timing_events_raw(None, None)
+            if args.step != "fused":
+                pspec.project(U, G, out=RG, M=MG)
+                pspec.project(U, HV, X=V, MX=MG, out=RH)
             pspec.retract(U, RG, t_step, out=Un)
             pspec.objective(dg, Un, p, F_col=Fc2, F=F)
 
@@ -284,21 +307,13 @@ def main() -> int:
         torch.cuda.synchronize()
         start.record()
         for i in range(steps):
-            if timed_kernel:
-                dg.set_timing_events_raw(*evs.pairs[i])
-            pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc)
-            if timed_kernel:
-                dg.set_timing_events_raw(None, None)
-            pspec.project(U, G, out=RG, M=MG)
-            pspec.project(U, HV, X=V, MX=MG, out=RH)
-            pspec.retract(U, RG, t_step, out=Un)
-            pspec.objective(dg, Un, p, F_col=Fc2, F=F)
+            step(evs.pairs[i] if timed_kernel else None)
         stop.record()
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(stop)
         edge_ms = [evs.elapsed_ms(i) for i in range(steps)] if timed_kernel else []
         evs.close()
-        ok = bool(torch.isfinite(F).item()) and bool(torch.isfinite(HV).all().item())
+        ok = bool(torch.isfinite(F).item()) and bool(torch.isfinite(RH).all().item())
         return total_ms / steps, edge_ms, ok
 
     if args.copy_calibration:
@@ -326,7 +341,7 @@ def main() -> int:
     edge_ms = float(np.mean(edge32))
     alg_bytes = algorithmic_edge_bytes(n, nnz, k)
     achieved = alg_bytes / (edge_ms * 1e-3) / 1e9
-    traffic = stored_traffic("sbm8m", args.layout)
+    traffic = stored_traffic(args.workload, args.layout)
     out = {
         "metric": METRIC,
         "value": nnz * k / (t32 * 1e-3),
@@ -341,14 +356,15 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "sbm8m: SBM n=8,000,000, 16 blocks, mean degree 12, w~U[0.5,1.5], k=16, p=1.1, eps=1e-8",
+            "workload": WORKLOADS[args.workload],
             "n": n,
             "nnz": nnz,
             "k": k,
             "p": p,
             "eps": eps,
             "layout": args.layout,
-            "step": "hvp(fused grad) + 2x project + retract + objective",
+            "step": ("rhvp (grad, HVP, both Grassmann projections)" if args.step == "fused" else
+                     "hvp (fused grad) + 2x project") + " + retract + objective",
             "edge_col_updates_per_step": nnz * k,
         },
         "roofline": {
@@ -358,7 +374,7 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "edge_light (fused grad+HVP edge pass)",
+            "kernel": "fused grad+HVP edge pass (light rows, heavy chunks, split-row combine)",
             "algorithmic_bytes_per_launch": alg_bytes,
             "launch_ms": edge_ms,
         },
@@ -367,7 +383,7 @@ def main() -> int:
         "speedup_fp32_over_fp64": (fp64["ms_per_step"] / t32) if fp64 else None,
         "finite": ok32,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "sbm8m":
         print("[bench] timing the CPU oracle on the sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out))

@@ -93,8 +93,8 @@ typedef struct ihipEvent_t *pspec_event;
  * memory (schedule, per-tile FP64 partial sums, chunk scratch): about
  * 8 * 4 * k_max * (n / 256 + chunks) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
  */
-#define PSPEC_LIGHT_MAX 1024
-#define PSPEC_CHUNK 2048
+#define PSPEC_LIGHT_MAX 32
+#define PSPEC_CHUNK 1024
 pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
                                 const void *w, pspec_dtype wtype, int k_max, pspec_stream stream,
                                 pspec_graph *out);
@@ -179,6 +179,26 @@ pspec_status pspec_project(int64_t n, int k, pspec_dtype dt, const void *U, int6
 pspec_status pspec_retract(int64_t n, int k, pspec_dtype dt, const void *U, int64_t ldu, const void *eta,
                            int64_t lde, double t, void *Uout, int64_t ldo, double *R, void *ws, size_t ws_bytes,
                            pspec_stream stream);
+
+/*
+ * pspec_rhvp -- Riemannian gradient and Riemannian Hessian-vector product of Eq. (1) on the
+ * Grassmann manifold at U (orthonormal columns), the quantities one truncated-CG iteration of the
+ * Newton method of Section 2 needs, in one call:
+ *   MG = U^T G                                   (k x k, FP64, row-major, written if MG != NULL)
+ *   RG = G - U MG                                (Riemannian gradient P_U(G))
+ *   RH = HV - U (U^T HV) - V MG                  (Riemannian Hessian P_U(H V) - V (U^T G))
+ * where G and HV are the outputs of pspec_hvp.  The results are bit-identical to pspec_hvp
+ * followed by pspec_project(U, G) and pspec_project(U, HV, X = V, MX = MG); the epilogue, the two
+ * Gram matrices and both projections share passes over the rows, and G and HV are never written.
+ *   V       n x k tangent direction (dt), leading dimension ldv (may be U + k with ldu = ldv).
+ *   RH, RG  n x k outputs (dt); both REQUIRED; neither may overlap U, V or each other.
+ *   F_col   device, k doubles (the objective per column), may be NULL.
+ *   ws      device workspace of pspec_dense_workspace_bytes(k) bytes, 256-byte aligned; shared
+ *           with no other call in flight.
+ */
+pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                        int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
+                        double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream);
 
 /* pspec_dot -- *out = sum_{i,l} A[i,l] B[i,l] (Frobenius inner product, FP64, fixed order). */
 pspec_status pspec_dot(int64_t n, int k, pspec_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb,

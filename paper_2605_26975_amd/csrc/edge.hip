@@ -20,6 +20,7 @@
 #include <utility>
 
 #include "common.hpp"
+#include "dense.hpp"
 
 namespace pspec {
 namespace {
@@ -85,27 +86,6 @@ struct Term {
     }
 };
 
-// Sum the FP64 per-lane accumulators over the lanes of one column and write the block's partial row.
-template <int K>
-__device__ __forceinline__ void write_partials(double q[kQ], double (*s_red)[kQ][K], double *prow, int k) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int o = K; o < 64; o <<= 1)
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) q[i] += __shfl_xor(q[i], o);
-    if (lane < K)
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) s_red[wave][i][lane] = q[i];
-    __syncthreads();
-    if (tid < kQ * K) {
-        const int i = tid / K, c = tid % K;
-        double s = 0.0;
-#pragma unroll
-        for (int wv = 0; wv < kBlock / 64; ++wv) s += s_red[wv][i][c];
-        if (c < k) prow[i * k + c] = s;
-    }
-}
-
 // ---- cross-lane helpers (VALU only: DPP broadcasts, readlane, permlane swaps) ---------------
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -154,20 +134,29 @@ __device__ __forceinline__ T edge_bcast_val(T v, int e, int lane) {
     }
 }
 
-// Light rows: a group of G lanes per row (K column lanes x G/K edge slots), kTileRows rows per
-// workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR ranges.
-// A row is walked in chunks of G edges: the group loads the chunk's neighbour ids and weights with
-// one coalesced load (lane l of the group takes edge l), hands them to the lanes that need them with
-// VALU broadcasts (DPP row broadcast for 16-lane groups, readlane for 32- and 64-lane groups), and
-// issues every gather of the chunk before using any.  The ids of the group's next row are loaded
-// before the current row's gathers, so a row costs one memory latency, not two.  The gather rate of
-// random neighbour rows, not HBM bandwidth, bounds this kernel on random graphs: keeping 4 rows per
-// wave (16-lane groups for k <= 16) in flight matters more than the width of each load.
+// Light rows: a group of G = 16 lanes (one DPP row) per row, four rows per wave, kTileRows rows
+// per workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR
+// ranges.  For k <= 16 the group is KL = K column lanes x G/KL edge slots; for k > 16 each lane
+// owns CPL = K/16 columns at stride 16, so every load is a coalesced 64-byte segment and four rows
+// per wave stay in flight whatever k is.  A row is walked in chunks of G edges: the group loads
+// the chunk's neighbour ids and weights with one coalesced load (lane l takes edge l), the loading
+// lane turns each id into byte offsets into U and V once, DPP row broadcasts hand offsets and
+// weights to the lanes that need them, and every gather of the chunk is issued before any is
+// used.  The group's next row (its own u_i, v_i and first-chunk ids) is loaded before the current
+// row's gathers.  The gather rate of random neighbour rows, not HBM bandwidth, bounds this kernel
+// on random graphs: rows in flight per wave matter more than the width of each load.
+template <int K>
+constexpr int light_cpl() {
+    return K > 16 ? K / 16 : 1;
+}
 
-template <typename T, typename WT, int K, int G, int MODE>
+template <typename T, typename WT, int K, int MODE>
 __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
-    constexpr int EPR = G / K;   // edge slots per row
-    constexpr int NU = G / EPR;  // shuffle steps per chunk of G edges (= K)
+    constexpr int G = 16;
+    constexpr int CPL = light_cpl<K>();  // columns per lane
+    constexpr int KL = K / CPL;          // column lanes per edge slot
+    constexpr int EPR = G / KL;          // edge slots per row
+    constexpr int NU = G / EPR;          // broadcast steps per chunk of G edges
     constexpr int NGRP = kBlock / G;
     constexpr int RS = kTileRows / NGRP;
     static_assert(kTileRows % NGRP == 0, "tile rows must split evenly over groups");
@@ -177,10 +166,13 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int grp = tid / G, gl = tid % G;
-    const int gbase = lane - gl;  // first lane of this group within the wave
-    const int c = gl % K, e = gl / K;
-    const int cl = c < a.k ? c : a.k - 1;
-    const uint32_t cb = (uint32_t)cl * (uint32_t)sizeof(T);
+    const int c = gl % KL, e = gl / KL;
+    uint32_t cb[CPL];  // byte offsets of this lane's columns (clamped to k - 1)
+#pragma unroll
+    for (int m = 0; m < CPL; ++m) {
+        const int cm = c + m * KL;
+        cb[m] = (uint32_t)(cm < a.k ? cm : a.k - 1) * (uint32_t)sizeof(T);
+    }
     const int64_t row0 = (int64_t)blockIdx.x * kTileRows;
     for (int t = tid; t <= kTileRows; t += kBlock) {
         const int64_t r = row0 + t;
@@ -190,23 +182,41 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
 
     const auto rU = make_rsrc(a.U, a.U_bytes);
     const auto rV = make_rsrc(a.V, a.V_bytes);
-    // ids and weights of the first chunk of local row rl (padding: the row itself, weight 0)
-    auto first_chunk = [&](int rl, int32_t &jl, T &wl) {
+    // What row rl needs before its gathers: own u_i, v_i, and the first chunk's neighbour offsets
+    // (padding: the row itself, weight 0).  Loaded one row ahead.
+    struct RowPre {
+        T ui[CPL], vi[CPL];
+        T wl;
+        uint32_t ou, ov;
+    };
+    auto prefetch = [&](int rl) {
+        RowPre r;
         const int64_t row = row0 + rl;
-        jl = row < a.n ? (int32_t)row : 0;
-        wl = (T)0;
-        if (row < a.n) {
+        const bool valid = row < a.n;
+        uint32_t j = valid ? (uint32_t)row : 0u;
+#pragma unroll
+        for (int m = 0; m < CPL; ++m) {
+            r.ui[m] = bload<T>(rU, j * a.ldu_b + cb[m]);
+            r.vi[m] = (MODE == HVP) ? bload<T>(rV, j * a.ldv_b + cb[m]) : (T)0;
+        }
+        r.wl = (T)0;
+        if (valid) {
             const int64_t b = s_rp[rl], d = s_rp[rl + 1] - b;
             if (d <= a.light_max && gl < d) {
-                jl = a.col[b + gl];
-                wl = (T)a.w[b + gl];
+                j = (uint32_t)a.col[b + gl];
+                r.wl = (T)a.w[b + gl];
             }
         }
+        r.ou = j * a.ldu_b;
+        r.ov = j * a.ldv_b;
+        return r;
     };
-    int32_t jl;
-    T wl;
-    first_chunk(grp, jl, wl);
-    double q[kQ] = {0.0, 0.0, 0.0, 0.0};  // N, D, a, S
+    RowPre nxt = prefetch(grp);
+    double q[kQ][CPL];  // N, D, a, S per owned column
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+#pragma unroll
+        for (int m = 0; m < CPL; ++m) q[i][m] = 0.0;
     for (int s = 0; s < RS; ++s) {
         const int rl = grp + s * NGRP;
         const int64_t row = row0 + rl;
@@ -215,31 +225,45 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
         const bool light = valid && (end - beg) <= a.light_max;
         const int64_t len = light ? end - beg : 0;
         const uint32_t own = valid ? (uint32_t)row : 0u;
-        const T ui = bload<T>(rU, own * a.ldu_b + cb);
-        T vi = 0;
-        if (MODE == HVP) vi = bload<T>(rV, own * a.ldv_b + cb);
-        int32_t jn = 0;
-        T wn = (T)0;
-        if (s + 1 < RS) first_chunk(rl + NGRP, jn, wn);  // prefetch the next row's ids
+        const RowPre cur = nxt;
+        if (s + 1 < RS) nxt = prefetch(rl + NGRP);
+        uint32_t ou = cur.ou, ov = cur.ov;
+        T wl = cur.wl;
         const int nch = (int)((len + G - 1) / G);
-        T Ls = 0, Js = 0, Ns = 0;
+        T Ls[CPL], Js[CPL], Ns[CPL];
+#pragma unroll
+        for (int m = 0; m < CPL; ++m) Ls[m] = Js[m] = Ns[m] = 0;
         for (int ch = 0; ch < nch; ++ch) {
-            const int64_t c0 = beg + (int64_t)ch * G;
             const int64_t rem = len - (int64_t)ch * G;
             const int cnt = rem <= 0 ? 0 : (rem < G ? (int)rem : G);
-            if (ch > 0) {
-                jl = gl < cnt ? a.col[c0 + gl] : (int32_t)own;
-                wl = gl < cnt ? (T)a.w[c0 + gl] : (T)0;
+            // offsets of the row's next chunk, loaded while this chunk's gathers are in flight
+            uint32_t ou2 = own * a.ldu_b, ov2 = own * a.ldv_b;
+            T wl2 = (T)0;
+            if (ch + 1 < nch) {
+                const int64_t c1 = beg + (int64_t)(ch + 1) * G;
+                if (c1 + gl < end) {
+                    const uint32_t j2 = (uint32_t)a.col[c1 + gl];
+                    ou2 = j2 * a.ldu_b;
+                    ov2 = j2 * a.ldv_b;
+                    wl2 = (T)a.w[c1 + gl];
+                }
             }
-            T uj[NU], vj[NU];
+            T uj[NU][CPL], vj[NU][CPL];
             static_for<0, NU>([&](auto uc) {
                 constexpr int u = decltype(uc)::value;
-                uj[u] = ui;
-                vj[u] = vi;
+#pragma unroll
+                for (int m = 0; m < CPL; ++m) {
+                    uj[u][m] = cur.ui[m];
+                    vj[u][m] = cur.vi[m];
+                }
                 if (u * EPR < cnt) {
-                    const int32_t j = edge_bcast<G, EPR, u>(jl, e, lane);
-                    uj[u] = bload<T>(rU, (uint32_t)j * a.ldu_b + cb);
-                    if (MODE == HVP) vj[u] = bload<T>(rV, (uint32_t)j * a.ldv_b + cb);
+                    const uint32_t bu = (uint32_t)edge_bcast<G, EPR, u>((int32_t)ou, e, lane);
+                    const uint32_t bv = (MODE == HVP) ? (uint32_t)edge_bcast<G, EPR, u>((int32_t)ov, e, lane) : 0u;
+#pragma unroll
+                    for (int m = 0; m < CPL; ++m) {
+                        uj[u][m] = bload<T>(rU, bu + cb[m]);
+                        if (MODE == HVP) vj[u][m] = bload<T>(rV, bv + cb[m]);
+                    }
                 }
             });
             // every gather of the chunk is in flight before the first one is used
@@ -247,50 +271,83 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
                 constexpr int u = decltype(uc)::value;
                 if (u * EPR < cnt) {
                     const T wv = edge_bcast_val<T, G, EPR, u>(wl, e, lane);
-                    Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wv, Ls, Js, Ns);
+#pragma unroll
+                    for (int m = 0; m < CPL; ++m)
+                        Term<T, MODE>::apply(a.pw, a.epsc, cur.ui[m], uj[u][m], cur.vi[m], vj[u][m], wv, Ls[m],
+                                             Js[m], Ns[m]);
                 }
             });
+            ou = ou2;
+            ov = ov2;
+            wl = wl2;
         }
-        jl = jn;
-        wl = wn;
-        if (EPR > 1) {
 #pragma unroll
-            for (int o = K; o < G; o <<= 1) {
-                if (MODE != OBJ) Ls += __shfl_xor(Ls, o);
-                if (MODE == HVP) Js += __shfl_xor(Js, o);
+        for (int m = 0; m < CPL; ++m) {
+            if (EPR > 1) {
+#pragma unroll
+                for (int o = KL; o < G; o <<= 1) {
+                    if (MODE != OBJ) Ls[m] += __shfl_xor(Ls[m], o);
+                    if (MODE == HVP) Js[m] += __shfl_xor(Js[m], o);
+                }
             }
-        }
-        q[0] += (double)Ns;
-        if (valid && e == 0) {
-            const T hi = a.pw(fabs(ui));
-            const T phi = hi * ui;  // phi_p(u_i)
-            q[1] += (double)(phi * ui);
-            if (MODE == HVP) {
-                q[2] += (double)phi * (double)vi;
-                if (light) q[3] += (double)Ls * (double)vi;
-            }
-            if (light && c < a.k) {
-                if (MODE != OBJ) a.L[row * a.ldl + c] = Ls;
-                if (MODE == HVP) a.J[row * a.ldj + c] = Js;
+            q[0][m] += (double)Ns[m];
+            if (valid && e == 0) {
+                const T ui = cur.ui[m], vi = cur.vi[m];
+                const T hi = a.pw(fabs(ui));
+                const T phi = hi * ui;  // phi_p(u_i)
+                q[1][m] += (double)(phi * ui);
+                if (MODE == HVP) {
+                    q[2][m] += (double)phi * (double)vi;
+                    if (light) q[3][m] += (double)Ls[m] * (double)vi;
+                }
+                const int cm = c + m * KL;
+                if (light && cm < a.k) {
+                    if (MODE != OBJ) a.L[row * a.ldl + cm] = Ls[m];
+                    if (MODE == HVP) a.J[row * a.ldj + cm] = Js[m];
+                }
             }
         }
     }
-    write_partials<K>(q, s_red, a.partials + (int64_t)blockIdx.x * kQ * a.k, a.k);
+    // sum the FP64 accumulators over the lanes of each column and write the block's partial row
+#pragma unroll
+    for (int o = KL; o < 64; o <<= 1)
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+#pragma unroll
+            for (int m = 0; m < CPL; ++m) q[i][m] += __shfl_xor(q[i][m], o);
+    const int wave = tid >> 6;
+    if (lane < KL)
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+#pragma unroll
+            for (int m = 0; m < CPL; ++m) s_red[wave][i][lane + m * KL] = q[i][m];
+    __syncthreads();
+    double *prow = a.partials + (int64_t)blockIdx.x * kQ * a.k;
+    for (int t = tid; t < kQ * K; t += kBlock) {
+        const int i = t / K, cc = t % K;
+        double sum = 0.0;
+#pragma unroll
+        for (int wv = 0; wv < kBlock / 64; ++wv) sum += s_red[wv][i][cc];
+        if (cc < a.k) prow[i * a.k + cc] = sum;
+    }
 }
 
-// Heavy rows: one workgroup per chunk of at most PSPEC_CHUNK edges.  The chunk's neighbour ids and
-// weights are staged in LDS with coalesced loads; the workgroup's 256/K edge slots then stream them.
+// Heavy rows: one workgroup per chunk of at most PSPEC_CHUNK edges.  The chunk's neighbour byte
+// offsets and weights are staged in LDS with coalesced loads; the workgroup's 256/K edge slots then
+// stream them with UNR gathers in flight per thread.
 template <typename T, typename WT, int K, int MODE, int UNR>
 __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
     constexpr int EPB = kBlock / K;
-    __shared__ int32_t s_col[PSPEC_CHUNK];
+    __shared__ uint32_t s_ou[PSPEC_CHUNK], s_ov[PSPEC_CHUNK];  // neighbour byte offsets into U, V
     __shared__ T s_w[PSPEC_CHUNK];
     __shared__ double s_r[3][kBlock];
     const Chunk ch = a.chunks[blockIdx.x];
     const int len = (int)(ch.end - ch.beg);
     const int tid = threadIdx.x;
     for (int t = tid; t < len; t += kBlock) {
-        s_col[t] = a.col[ch.beg + t];
+        const uint32_t j = (uint32_t)a.col[ch.beg + t];
+        s_ou[t] = j * a.ldu_b;
+        s_ov[t] = j * a.ldv_b;
         s_w[t] = (T)a.w[ch.beg + t];
     }
     __syncthreads();
@@ -305,20 +362,14 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
     if (MODE == HVP) vi = bload<T>(rV, row * a.ldv_b + cb);
     T Ls = 0, Js = 0, Ns = 0;
     for (int base = 0; base < len; base += EPB * UNR) {
-        int32_t j[UNR];
-        T wv[UNR];
+        T uj[UNR], vj[UNR], wv[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int idx = base + u * EPB + e;
             const bool ok = idx < len;
-            j[u] = ok ? s_col[idx] : (int32_t)row;
             wv[u] = ok ? s_w[idx] : (T)0;
-        }
-        T uj[UNR], vj[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            uj[u] = bload<T>(rU, (uint32_t)j[u] * a.ldu_b + cb);
-            vj[u] = (MODE == HVP) ? bload<T>(rV, (uint32_t)j[u] * a.ldv_b + cb) : (T)0;
+            uj[u] = ok ? bload<T>(rU, s_ou[idx] + cb) : ui;
+            vj[u] = (MODE == HVP && ok) ? bload<T>(rV, s_ov[idx] + cb) : vi;
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wv[u], Ls, Js, Ns);
@@ -424,7 +475,34 @@ __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict
     }
 }
 
-// Epilogue: G (and HV) from the raw rows and the per-column scalars; K lanes per row.
+// Per-column scalars of the epilogue, read from Graph::scalars.
+struct ColScalars {
+    double pD, F, a, b;
+};
+__device__ __forceinline__ ColScalars col_scalars(const double *__restrict__ sc, int k_max, int c) {
+    return {sc[SC_PD * k_max + c], sc[SC_F * k_max + c], sc[SC_A * k_max + c], sc[SC_B * k_max + c]};
+}
+
+// Epilogue of one entry: from u_i, v_i and the raw rows L_i = (Delta_p u)_i, J_i (edge part of the
+// Hessian over p - 1), the gradient g = (p/D)(L - F phi_p(u)) and
+// HV = (p/D)((p-1) J - F (p-1) psi(u) v - g a - phi_p(u) b), both rounded to T.  Every kernel that
+// forms these entries goes through this function, so they agree bit for bit.
+template <typename T, int MODE>
+__device__ __forceinline__ void epilogue(const PowM2<T> &pw, T epsc, double p, const ColScalars &s, T u, T v, T l,
+                                         T j, T &gout, T &hout) {
+    const T h = pw(fabs(u));
+    const T phi = h * u;
+    const double g = s.pD * ((double)l - s.F * (double)phi);
+    gout = (T)g;
+    if (MODE == HVP) {
+        const T psi = fmin(h, epsc);
+        const double hv = s.pD * ((p - 1.0) * (double)j - s.F * (p - 1.0) * (double)psi * (double)v - g * s.a -
+                                  (double)phi * s.b);
+        hout = (T)hv;
+    }
+}
+
+// Epilogue over all rows: G (and HV) in place of the raw rows; K lanes per row.
 template <typename T, int K, int MODE>
 __global__ __launch_bounds__(kBlock) void finalize(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
                                                  const T *__restrict__ V, int64_t ldv, T *__restrict__ G, int64_t ldg,
@@ -433,30 +511,149 @@ __global__ __launch_bounds__(kBlock) void finalize(int64_t n, int k, const T *__
     const int64_t stride = (int64_t)gridDim.x * (kBlock / K);
     const int c = threadIdx.x % K;
     if (c >= k) return;
-    const double pD = sc[SC_PD * k_max + c], F = sc[SC_F * k_max + c];
-    const double av = sc[SC_A * k_max + c], bv = sc[SC_B * k_max + c];
+    const ColScalars cs = col_scalars(sc, k_max, c);
     for (int64_t i = (int64_t)blockIdx.x * (kBlock / K) + threadIdx.x / K; i < n; i += stride) {
-        const T u = U[i * ldu + c];
-        const T h = pw(fabs(u));
-        const T phi = h * u;
-        const double g = pD * ((double)G[i * ldg + c] - F * (double)phi);
-        G[i * ldg + c] = (T)g;
-        if (MODE == HVP) {
-            const T v = V[i * ldv + c];
-            const T psi = fmin(h, epsc);
-            const double hv =
-                pD * ((p - 1.0) * (double)HV[i * ldh + c] - F * (p - 1.0) * (double)psi * (double)v - g * av -
-                      (double)phi * bv);
-            HV[i * ldh + c] = (T)hv;
-        }
+        const T v = MODE == HVP ? V[i * ldv + c] : T(0);
+        const T j = MODE == HVP ? HV[i * ldh + c] : T(0);
+        T g, hv;
+        epilogue<T, MODE>(pw, epsc, p, cs, U[i * ldu + c], v, G[i * ldg + c], j, g, hv);
+        G[i * ldg + c] = g;
+        if (MODE == HVP) HV[i * ldh + c] = hv;
     }
 }
 
-template <int K>
-constexpr int light_group() {
-    return K <= 16 ? 16 : K;
+// Fused epilogue and Gram matrices of the Riemannian Hessian-vector product: per workgroup (a fixed
+// grid of kDenseBlocks, each over a contiguous row range) the FP64 partials of U^T G and U^T HV,
+// with G and HV formed from the raw rows L, J by the epilogue above and kept in LDS only.  The row
+// ranges, tiles and accumulation order are those of the stand-alone Gram kernel, so the sums equal
+// the Gram matrices of the finalized G and HV bit for bit.
+template <typename T, int K, bool VEC>
+__global__ __launch_bounds__(kBlock) void finalize_gram(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
+                                                      const T *__restrict__ V, int64_t ldv, const T *__restrict__ L,
+                                                      int64_t ldl, const T *__restrict__ J, int64_t ldj, PowM2<T> pw,
+                                                      T epsc, double p, const double *__restrict__ sc, int k_max,
+                                                      double *__restrict__ part) {
+    using Geo = GramGeom<T, K, VEC>;
+    constexpr int TR = Geo::TR, W = Geo::W, CV = Geo::CV, PER = Geo::PER;
+    constexpr size_t TILE_BYTES = (size_t)TR * K * sizeof(T) * 3;
+    __shared__ __align__(16) unsigned char smem[TILE_BYTES > Geo::RED_BYTES ? TILE_BYTES : Geo::RED_BYTES];
+    T(*sU)[K] = reinterpret_cast<T(*)[K]>(smem);
+    T(*sG)[K] = reinterpret_cast<T(*)[K]>(smem + (size_t)TR * K * sizeof(T));
+    T(*sH)[K] = reinterpret_cast<T(*)[K]>(smem + 2 * (size_t)TR * K * sizeof(T));
+    const int tid = threadIdx.x, sub = tid % Geo::TPR, rg = tid / Geo::TPR;
+    const int a0 = (sub / Geo::NS) * 4, b0 = (sub % Geo::NS) * 4;
+    const int c = (tid % CV) * W;  // this thread's columns, the same for all its vectors
+    ColScalars cs[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) cs[q] = c + q < k ? col_scalars(sc, k_max, c + q) : ColScalars{0.0, 0.0, 0.0, 0.0};
+    int64_t r0, r1;
+    block_rows(n, r0, r1);
+    double acc[2][4][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int p2 = 0; p2 < 4; ++p2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[m][p2][q] = 0.0;
+    T xu[PER][W], xv[PER][W], xl[PER][W], xj[PER][W];
+    auto fetch = [&](int64_t t0) {
+#pragma unroll
+        for (int v = 0; v < PER; ++v) {
+            const int64_t i = t0 + (tid + v * kBlock) / CV;
+#pragma unroll
+            for (int q = 0; q < W; ++q) xu[v][q] = xv[v][q] = xl[v][q] = xj[v][q] = T(0);
+            if (i < r1) {
+                load_cols<T, W, VEC>(U + i * ldu, c, k, xu[v]);
+                load_cols<T, W, VEC>(V + i * ldv, c, k, xv[v]);
+                load_cols<T, W, VEC>(L + i * ldl, c, k, xl[v]);
+                load_cols<T, W, VEC>(J + i * ldj, c, k, xj[v]);
+            }
+        }
+    };
+    if (r0 < r1) fetch(r0);
+    for (int64_t t0 = r0; t0 < r1; t0 += TR) {
+#pragma unroll
+        for (int v = 0; v < PER; ++v) {
+            const int r = (tid + v * kBlock) / CV;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                T g, hv;
+                epilogue<T, HVP>(pw, epsc, p, cs[q], xu[v][q], xv[v][q], xl[v][q], xj[v][q], g, hv);
+                // rows past the range and padded columns stay zero, as in the stand-alone Gram
+                const bool live = t0 + r < r1 && c + q < k;
+                sU[r][c + q] = xu[v][q];
+                sG[r][c + q] = live ? g : T(0);
+                sH[r][c + q] = live ? hv : T(0);
+            }
+        }
+        __syncthreads();
+        if (t0 + TR < r1) fetch(t0 + TR);
+        gram_tile<T, K, TR, 2>(sU, sG, sH, rg, a0, b0, acc);
+        __syncthreads();
+    }
+    gram_block_reduce<K, 2>(acc, reinterpret_cast<double(*)[gram_red<K>()][16]>(smem), k,
+                            part + (int64_t)blockIdx.x * 2 * k * k);
 }
-constexpr int kUnroll = 4;
+
+// Projection of the fused Riemannian Hessian-vector product, one lane per row:
+//   RG_i = G_i - U_i MG,   RH_i = HV_i - U_i MH - V_i MG,   MG = U^T G, MH = U^T HV,
+// with G_i and HV_i formed again from the raw rows (held in RG and RH on entry, overwritten in
+// place) by the shared epilogue.  The products run in the order of the stand-alone projection.
+template <typename T, int K, bool VEC>
+__global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
+                                                   const T *__restrict__ V, int64_t ldv, T *__restrict__ RG,
+                                                   int64_t ldrg, T *__restrict__ RH, int64_t ldrh, PowM2<T> pw, T epsc,
+                                                   double p, const double *__restrict__ sc, int k_max,
+                                                   const double *__restrict__ MG, const double *__restrict__ MH) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T u[K], v[K], g[K], hv[K];
+    load_row<T, K, VEC>(U + i * ldu, k, u);
+    load_row<T, K, VEC>(V + i * ldv, k, v);
+    load_row<T, K, VEC>(RG + i * ldrg, k, g);
+    load_row<T, K, VEC>(RH + i * ldrh, k, hv);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const ColScalars cs = c < k ? col_scalars(sc, k_max, c) : ColScalars{0.0, 0.0, 0.0, 0.0};
+        epilogue<T, HVP>(pw, epsc, p, cs, u[c], v[c], g[c], hv[c], g[c], hv[c]);
+    }
+    T res[K];
+    {
+        double o[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) o[c] = 0.0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const double ur = -1.0 * (double)u[r];
+#pragma unroll
+            for (int c = 0; c < K; ++c) o[c] = fma(ur, mat_at<K, VEC>(MG, k, r, c), o[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) res[c] = (T)fma(1.0, (double)g[c], o[c]);
+        store_row<T, K, VEC>(RG + i * ldrg, k, res);
+    }
+    double o[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) o[c] = 0.0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const double ur = -1.0 * (double)u[r];
+#pragma unroll
+        for (int c = 0; c < K; ++c) o[c] = fma(ur, mat_at<K, VEC>(MH, k, r, c), o[c]);
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        const double vr = -1.0 * (double)v[r];
+#pragma unroll
+        for (int c = 0; c < K; ++c) o[c] = fma(vr, mat_at<K, VEC>(MG, k, r, c), o[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) res[c] = (T)fma(1.0, (double)hv[c], o[c]);
+    store_row<T, K, VEC>(RH + i * ldrh, k, res);
+}
+
+constexpr int kUnroll = 8;  // gathers in flight per thread in the heavy-chunk kernel
 
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
     int64_t g = (items + per_block - 1) / per_block;
@@ -464,9 +661,11 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
     return (unsigned)(g < cap ? g : cap);
 }
 
+// The edge pass proper: edge kernels, split-row combine and the reductions to the per-column
+// scalars; L and J receive the raw rows.
 template <typename T, typename WT, int K, int MODE>
-pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J,
-                          int64_t ldj, double p, double eps, double *F_col, double *F, hipStream_t s) {
+pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J, int64_t ldj,
+               double p, double eps, double *F_col, double *F, hipStream_t s) {
     EdgeArgs<T, WT> a;
     a.rowptr = g->rowptr;
     a.col = g->col;
@@ -492,7 +691,7 @@ pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, 
     a.k_max = g->k_max;
     a.part_base = g->tiles;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
-    edge_light<T, WT, K, light_group<K>(), MODE><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
+    edge_light<T, WT, K, MODE><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     if (g->n_chunks > 0) edge_heavy<T, WT, K, MODE, kUnroll><<<(unsigned)g->n_chunks, kBlock, 0, s>>>(a);
     if (g->n_split > 0 && MODE != OBJ)
         combine_split<T, MODE><<<grid_for(g->n_split * k, kBlock, 1 << 30), kBlock, 0, s>>>(
@@ -501,12 +700,68 @@ pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, 
     const int W = kQ * k;
     reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + g->n_chunks, W, g->red1);
     reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F);
+    return PSPEC_OK;
+}
+
+template <typename T, typename WT, int K, int MODE>
+pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J,
+                          int64_t ldj, double p, double eps, double *F_col, double *F, hipStream_t s) {
+    const pspec_status st = edge_pass<T, WT, K, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
+    if (st != PSPEC_OK) return st;
     if (MODE != OBJ) {
         PowM2<T> pw;
         pw.pm2 = (T)(p - 2.0);
         const T epsc = (T)std::pow(eps, p - 2.0);
         finalize<T, K, MODE><<<grid_for(g->n, kBlock / K, 65536), kBlock, 0, s>>>(
             g->n, k, U, ldu, V, ldv, L, ldl, J, ldj, pw, epsc, p, g->scalars, g->k_max);
+    }
+    PSPEC_HIP(hipGetLastError());
+    return PSPEC_OK;
+}
+
+// The fused epilogue fits in registers while a lane holds four rows of at most 128 bytes.
+template <typename T, int K>
+constexpr bool rhvp_fused() {
+    return K * (int)sizeof(T) <= 128;
+}
+
+// Riemannian gradient and Hessian-vector product on Gr(k, n).  Workspace: level-1 partials
+// [kDenseBlocks][2][k*k], level-2 partials, then MG = U^T G and MH = U^T HV (k*k each).
+template <typename T, typename WT, int K, bool VEC>
+pspec_status launch_rhvp(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, double p, double eps, T *RH,
+                 int64_t ldrh, T *RG, int64_t ldrg, double *MG_out, double *F_col, double *ws, hipStream_t s) {
+    const int64_t n = g->n;
+    const size_t kk = (size_t)k * k;
+    double *part = ws;
+    double *mid = part + (size_t)kDenseBlocks * 2 * kk;
+    double *Mw = mid + (size_t)(kDenseBlocks / kTreeFan) * 2 * kk;  // [MG | MH]
+    PowM2<T> pw;
+    pw.pm2 = (T)(p - 2.0);
+    const T epsc = (T)std::pow(eps, p - 2.0);
+    const pspec_status st = edge_pass<T, WT, K, HVP>(g, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, p, eps, F_col, nullptr, s);
+    if (st != PSPEC_OK) return st;
+    const unsigned rows = (unsigned)((n + kBlock - 1) / kBlock);
+    if constexpr (rhvp_fused<T, K>()) {
+        finalize_gram<T, K, VEC><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc,
+                                                                 p, g->scalars, g->k_max, part);
+        sum_partials(part, (int)kk, mid, Mw, MG_out, s, 2 * (int64_t)kk);
+        sum_partials(part + kk, (int)kk, mid, Mw + kk, nullptr, s, 2 * (int64_t)kk);
+        apply_rhvp<T, K, VEC><<<rows, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc, p,
+                                                      g->scalars, g->k_max, Mw, Mw + kk);
+    } else {  // wide rows: finalize, then the two projections with the stand-alone kernels, in place
+        finalize<T, K, HVP><<<grid_for(n, kBlock / K, 65536), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH,
+                                                                               ldrh, pw, epsc, p, g->scalars,
+                                                                               g->k_max);
+        gram_partial<T, K, VEC, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RG,
+                                                                               ldrg, part);
+        sum_partials(part, (int)kk, mid, Mw, MG_out, s);
+        gram_partial<T, K, VEC, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RH,
+                                                                               ldrh, part);
+        sum_partials(part, (int)kk, mid, Mw + kk, nullptr, s);
+        apply_rows<T, K, VEC, false, false, true><<<rows, kBlock, 0, s>>>(
+            n, k, 1.0, RG, ldrg, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr, 0, nullptr, 0.0, RG, ldrg);
+        apply_rows<T, K, VEC, false, true, true><<<rows, kBlock, 0, s>>>(
+            n, k, 1.0, RH, ldrh, U, ldu, nullptr, 0, 0.0, Mw + kk, -1.0, V, ldv, Mw, -1.0, RH, ldrh);
     }
     PSPEC_HIP(hipGetLastError());
     return PSPEC_OK;
@@ -539,7 +794,35 @@ pspec_status dispatch(Graph *g, pspec_dtype dt, int k, const void *U, int64_t ld
                                             (double *)J, ldj, p, eps, F_col, F, s);
 }
 
-// Host-side argument checks shared by the three entry points.
+template <typename T, typename WT, int K>
+pspec_status rhvp_layout(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, double p, double eps,
+                         T *RH, int64_t ldrh, T *RG, int64_t ldrg, double *MG, double *F_col, double *ws,
+                         hipStream_t s) {
+    if (rows_vectorisable<T, K>(k, {{U, ldu}, {V, ldv}, {RH, ldrh}, {RG, ldrg}}))
+        return launch_rhvp<T, WT, K, true>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, s);
+    return launch_rhvp<T, WT, K, false>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, s);
+}
+
+template <typename T, typename WT>
+pspec_status rhvp_k(Graph *g, int k, const void *U, int64_t ldu, const void *V, int64_t ldv, double p, double eps,
+                    void *RH, int64_t ldrh, void *RG, int64_t ldrg, double *MG, double *F_col, double *ws,
+                    hipStream_t s) {
+#define PSPEC_RHVP_K(KK)                                                                                          \
+    case KK:                                                                                                      \
+        return rhvp_layout<T, WT, KK>(g, k, (const T *)U, ldu, (const T *)V, ldv, p, eps, (T *)RH, ldrh, (T *)RG, \
+                                      ldrg, MG, F_col, ws, s);
+    switch (pad_k(k)) {
+        PSPEC_RHVP_K(4)
+        PSPEC_RHVP_K(8)
+        PSPEC_RHVP_K(16)
+        PSPEC_RHVP_K(32)
+        PSPEC_RHVP_K(64)
+        default: set_error("unsupported k = %d", k); return PSPEC_ERR_UNSUPPORTED;
+    }
+#undef PSPEC_RHVP_K
+}
+
+// Host-side argument checks shared by the entry points.
 pspec_status check_common(Graph *g, pspec_dtype dt, int k, const void *U, int64_t ldu, double p, const char *who) {
     PSPEC_ARG(g != nullptr, "%s: NULL graph", who);
     PSPEC_ARG(dt == PSPEC_F32 || dt == PSPEC_F64, "%s: bad dtype %d", who, (int)dt);
@@ -608,4 +891,34 @@ extern "C" pspec_status pspec_hvp(pspec_graph g, pspec_dtype dt, int k, const vo
               "hvp: HV and G must not overlap U, V or each other");
     return dispatch<HVP>(g, dt, k, U, ldu, V, ldv, G, ldg, HV, ldh, p, eps, F_col, nullptr,
                          reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                                   int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
+                                   double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream) {
+    clear_error();
+    pspec_status st = check_common(g, dt, k, U, ldu, p, "rhvp");
+    if (st != PSPEC_OK) return st;
+    PSPEC_ARG(eps > 0.0 && std::isfinite(eps), "rhvp: eps = %g must be positive", eps);
+    if ((st = check_out(g, dt, k, V, ldv, "V", "rhvp")) != PSPEC_OK) return st;
+    if ((st = check_out(g, dt, k, RH, ldrh, "RH", "rhvp")) != PSPEC_OK) return st;
+    if ((st = check_out(g, dt, k, RG, ldrg, "RG", "rhvp")) != PSPEC_OK) return st;
+    PSPEC_ARG(ws != nullptr, "rhvp: workspace is NULL");
+    PSPEC_ARG(((uintptr_t)ws % 256) == 0, "rhvp: workspace must be 256-byte aligned");
+    if (ws_bytes < dense_ws_doubles(k) * sizeof(double)) {
+        set_error("rhvp: workspace of %zu bytes < %zu needed", ws_bytes, dense_ws_doubles(k) * sizeof(double));
+        return PSPEC_ERR_WORKSPACE;
+    }
+    const size_t es = dt == PSPEC_F32 ? 4 : 8;
+    const int64_t n = g->n;
+    PSPEC_ARG(!blocks_overlap(RH, ldrh, U, ldu, n, k, es) && !blocks_overlap(RH, ldrh, V, ldv, n, k, es) &&
+                  !blocks_overlap(RG, ldrg, U, ldu, n, k, es) && !blocks_overlap(RG, ldrg, V, ldv, n, k, es) &&
+                  !blocks_overlap(RG, ldrg, RH, ldrh, n, k, es),
+              "rhvp: RH and RG must not overlap U, V or each other");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    double *w = static_cast<double *>(ws);
+    if (dt == PSPEC_F32) return rhvp_k<float, float>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
+    if (g->wtype == PSPEC_F32)
+        return rhvp_k<double, float>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
+    return rhvp_k<double, double>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
 }

@@ -69,9 +69,10 @@ class Solver:
         return float(pspec.dot(A, B).item())
 
     def hess(self, U, p, X, out):
-        """Riemannian Hessian at U applied to the tangent vector X (uses self.MG = U^T G)."""
-        pspec.hvp(self.graph, U, X, p, self.eps, HV=self.HV, G=self.G)
-        pspec.project(U, self.HV, X=X, MX=self.MG, out=out)
+        """Riemannian Hessian at U applied to the tangent vector X: one fused library call (edge
+        pass, epilogue, both Gram matrices and the projection); the Riemannian gradient it also
+        returns goes to a scratch block."""
+        pspec.rhvp(self.graph, U, X, p, self.eps, RH=out, RG=self.HV, MG=self.MG)
         return out
 
     def newton(self, U: torch.Tensor, p: float, opt: NewtonOptions | None = None) -> tuple[torch.Tensor, NewtonInfo]:

@@ -17,8 +17,8 @@ LIB_PATH = os.environ.get("PSPEC_LIBRARY") or os.path.join(os.path.dirname(os.pa
 
 PSPEC_F32, PSPEC_F64 = 0, 1
 _STATUS = {0: "PSPEC_OK", 1: "PSPEC_ERR_ARG", 2: "PSPEC_ERR_UNSUPPORTED", 3: "PSPEC_ERR_HIP", 4: "PSPEC_ERR_WORKSPACE"}
-LIGHT_MAX = 1024
-CHUNK = 2048
+LIGHT_MAX = 32
+CHUNK = 1024
 K_MAX = 64
 
 _lib = None
@@ -47,6 +47,7 @@ def lib() -> ctypes.CDLL:
         "pspec_objective": [vp, i32, i32, vp, i64, dbl, vp, vp, vp],
         "pspec_grad": [vp, i32, i32, vp, i64, dbl, vp, i64, vp, vp],
         "pspec_hvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp],
+        "pspec_rhvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp, sz, vp],
         "pspec_project": [i64, i32, i32, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, sz, vp],
         "pspec_retract": [i64, i32, i32, vp, i64, vp, i64, dbl, vp, i64, vp, vp, sz, vp],
         "pspec_dot": [i64, i32, i32, vp, i64, vp, i64, vp, vp, sz, vp],
@@ -69,7 +70,7 @@ def exported_symbols() -> list[str]:
     return [
         "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info", "pspec_graph_set_timing_events",
         "pspec_objective", "pspec_grad",
-        "pspec_hvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
+        "pspec_hvp", "pspec_rhvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
         "pspec_axpby", "pspec_last_error",
     ]
 
@@ -213,6 +214,28 @@ def hvp(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float = 1
                            HV.data_ptr(), _block(HV, "HV"), G.data_ptr(), _block(G, "G"), F_col.data_ptr(),
                            _stream(U.device)))
     return HV, G, F_col
+
+
+def rhvp(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float = 1e-8,
+         RH: torch.Tensor | None = None, RG: torch.Tensor | None = None, MG: torch.Tensor | None = None,
+         F_col: torch.Tensor | None = None):
+    """Riemannian Hessian at U applied to the tangent vector V and Riemannian gradient, fused:
+    returns (RH = P_U(H V) - V (U^T G), RG = P_U(G), MG = U^T G, F_col)."""
+    ldu, ldv = _block(U, "U"), _block(V, "V")
+    k = U.shape[1]
+    if RH is None:
+        RH = torch.empty(U.shape, dtype=U.dtype, device=U.device)
+    if RG is None:
+        RG = torch.empty(U.shape, dtype=U.dtype, device=U.device)
+    if MG is None:
+        MG = torch.empty((k, k), dtype=torch.float64, device=U.device)
+    if F_col is None:
+        F_col = torch.empty(k, dtype=torch.float64, device=U.device)
+    ws = _dense_ws(U.device, k)
+    _check(lib().pspec_rhvp(graph.handle, _dtype_code(U), k, U.data_ptr(), ldu, V.data_ptr(), ldv, float(p),
+                            float(eps), RH.data_ptr(), _block(RH, "RH"), RG.data_ptr(), _block(RG, "RG"),
+                            MG.data_ptr(), F_col.data_ptr(), ws.data_ptr(), ws.numel(), _stream(U.device)))
+    return RH, RG, MG, F_col
 
 
 def project(U: torch.Tensor, Z: torch.Tensor, X: torch.Tensor | None = None, MX: torch.Tensor | None = None,

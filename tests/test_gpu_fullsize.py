@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2605_26975_amd import gen
+from paper_2605_26975_amd import gen, pspec
 from tests import gpu_util as gu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -34,6 +34,17 @@ def test_fullsize_vs_oracle(name):
         print(f"{name} {dtype}: F {eF:.2e}  G {eG:.2e}  HV {eH:.2e}", flush=True)
         assert eF < tol_fg and eG < tol_fg and eH < tol_hv, (eF, eG, eH)
         del HV, G
+    # the fused Riemannian call equals the unfused sequence bit for bit at full size
+    P = torch.empty((g.n, 2 * k), dtype=torch.float32, device="cuda")
+    P[:, :k] = torch.as_tensor(U)
+    P[:, k:] = torch.as_tensor(V)
+    Ut, Vt = P[:, :k], P[:, k:]
+    RH, RG, MG, _ = pspec.rhvp(dg, Ut, Vt, p, eps)
+    HV, G, _ = pspec.hvp(dg, Ut, Vt, p, eps)
+    RG2, MG2 = pspec.project(Ut, G)
+    RH2, _ = pspec.project(Ut, HV, X=Vt, MX=MG2)
+    assert torch.equal(RG, RG2) and torch.equal(MG, MG2) and torch.equal(RH, RH2)
+    del P, RH, RG, HV, G, RG2, RH2
     if name == "rmat22":
         assert info["heavy_rows"] > 0 and info["split_rows"] > 0
         HV, G, Fc = gu.gpu_hvp(dg, U, V, p, eps, torch.float32, layout="separate")

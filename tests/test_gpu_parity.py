@@ -60,13 +60,15 @@ def test_multitile_ragged(k, layout):
 
 
 def _hub_graph():
-    """Light rows plus hubs of degree 1024 (light limit), 1025, 1500 (one heavy chunk) and 5000
-    (three chunks, combined afterwards)."""
+    """Light rows plus hubs of degree LIGHT_MAX (the light limit), LIGHT_MAX + 1 and 300 (one heavy
+    chunk), CHUNK (exactly one chunk), CHUNK + 1 (two chunks) and 5000 (several chunks, combined
+    afterwards)."""
     rng = np.random.default_rng(5)
     n = 6000
     i = [rng.integers(0, n, 30000)]
     j = [rng.integers(0, n, 30000)]
-    for hub, deg in ((0, 5000), (1, 1500), (2, 1024), (3, 1025)):
+    L, C = pspec.LIGHT_MAX, pspec.CHUNK
+    for hub, deg in ((0, 5000), (1, C + 1), (2, C), (3, 300), (4, L + 1), (5, L)):
         nb = rng.choice(np.arange(10, n), size=deg, replace=False)
         i.append(np.full(deg, hub))
         j.append(nb)
@@ -86,7 +88,7 @@ def test_heavy_and_split_rows(k):
     assert info["heavy_rows"] == int(np.sum(deg > pspec.LIGHT_MAX))
     assert info["split_rows"] == int(np.sum(deg > pspec.CHUNK))
     assert info["chunks"] == int(np.sum(np.where(deg > pspec.LIGHT_MAX, (deg + pspec.CHUNK - 1) // pspec.CHUNK, 0)))
-    assert info["split_rows"] >= 1 and info["heavy_rows"] >= 3
+    assert info["split_rows"] >= 2 and info["heavy_rows"] >= 5
     for dtype, tol in ((torch.float64, F64_TOL), (torch.float32, F32_TOL_G)):
         e = gu.compare(g, k, 1.2, 1e-8, dtype, dg=dg)
         assert e["F"] < tol and e["G"] < tol, (dtype, e)
@@ -284,3 +286,40 @@ def test_project_and_retract_vs_oracle(dtype, k):
     pspec.retract(Uc, eta, 0.3, out=Uc)  # in place
     assert gu.rel(Uc.double().cpu().numpy(), orc.retract(Uh, eta.double().cpu().numpy(), 0.3)) < (
         3e-6 if dtype == torch.float32 else 1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_dense_strided_layouts_are_bit_identical(dtype):
+    """The dense kernels move rows as 16-byte vectors when every leading dimension allows it and
+    element by element otherwise; both visit the rows and columns in the same order, so contiguous
+    blocks, column slices of a 2k-wide buffer (vector path) and slices with ld = k + 1 (element
+    path) give identical bits."""
+    k, n = 16, 3001
+    print(f"[case] dense strided {dtype}", flush=True)
+    rng = np.random.default_rng(7)
+    U64, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    blocks = {nm: torch.as_tensor(a).to(dtype).cuda() for nm, a in
+              (("U", U64), ("Z", rng.standard_normal((n, k))), ("X", rng.standard_normal((n, k))))}
+    MX = torch.as_tensor(rng.standard_normal((k, k))).cuda()
+
+    def laid_out(width):
+        out = {}
+        for nm, a in blocks.items():
+            buf = torch.full((n, width), float("nan"), dtype=dtype, device="cuda")
+            buf[:, :k] = a
+            out[nm] = buf[:, :k]
+        return out
+
+    def run(b):
+        P, M = pspec.project(b["U"], b["Z"], X=b["X"], MX=MX)
+        Q, R = pspec.retract(b["U"], b["Z"], 0.7)
+        d = pspec.dot(b["Z"], b["X"])
+        Y = b["Z"].clone()
+        pspec.axpby(0.5, b["X"], -2.0, Y)
+        return [P, M, Q, R, d, Y]
+
+    ref = run(blocks)
+    for width in (2 * k, k + 1):
+        got = run(laid_out(width))
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), width

@@ -1,0 +1,102 @@
+"""GPU: the fused Riemannian gradient and Hessian-vector product (pspec_rhvp) against the unfused
+sequence pspec_hvp -> pspec_project(G) -> pspec_project(HV, X = V, MX = U^T G), bit for bit, and
+against the FP64 oracle's Grassmann formulas (tangent projection and Riemannian Hessian)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from paper_2605_26975_amd import gen, pspec
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+def _tangent_pair(n, k, seed):
+    """U with orthonormal columns and V = P_U(V0) tangent at U, both FP64."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    V0 = rng.standard_normal((n, k))
+    return U, V0 - U @ (U.T @ V0)
+
+
+def _place(U, V, dtype, layout):
+    k = U.shape[1]
+    if layout == "interleaved":
+        P = torch.empty((U.shape[0], 2 * k), dtype=dtype, device="cuda")
+        P[:, :k] = torch.as_tensor(U).to(dtype)
+        P[:, k:] = torch.as_tensor(V).to(dtype)
+        return P[:, :k], P[:, k:]
+    return torch.as_tensor(U).to(dtype).cuda(), torch.as_tensor(V).to(dtype).cuda()
+
+
+def _unfused(dg, U, V, p, eps):
+    HV, G, Fc = pspec.hvp(dg, U, V, p, eps)
+    RG, MG = pspec.project(U, G)
+    RH, _ = pspec.project(U, HV, X=V, MX=MG)
+    return RH, RG, MG, Fc
+
+
+_GRAPHS = {
+    "sbm20k": lambda: gen.sbm_edges(20_000, 8, 100_000, 12_000, 0.5, 1.5, seed=11),
+    "sbm1000": lambda: gen.sbm_bernoulli(1000, 4, 0.05, 0.002),
+}
+
+
+@pytest.mark.parametrize("layout", ["separate", "interleaved"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("k", [3, 5, 16, 32, 64])
+@pytest.mark.parametrize("graph", ["sbm20k", "sbm1000"])
+def test_rhvp_bit_identical_to_hvp_and_projections(graph, k, dtype, layout):
+    """Covers the 16-byte and element paths (k a multiple of 4 or not), the register-fused kernels
+    (rows of at most 128 bytes) and the stand-alone fallback (FP32 k = 64, FP64 k >= 32), and
+    fewer rows than Gram workgroups (n = 1000)."""
+    print(f"[case] rhvp bitwise {graph} k={k} {dtype} {layout}", flush=True)
+    g = _GRAPHS[graph]()
+    Uh, Vh = _tangent_pair(g.n, k, seed=k)
+    dg = gu.device_graph(g, k)
+    U, V = _place(Uh, Vh, dtype, layout)
+    p, eps = 1.3, 1e-8
+    got = pspec.rhvp(dg, U, V, p, eps)
+    ref = _unfused(dg, U, V, p, eps)
+    for name, a, b in zip(("RH", "RG", "MG", "F_col"), got, ref):
+        assert torch.equal(a, b), name
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_rhvp_vs_oracle(dtype):
+    g = gen.sbm_edges(30_000, 8, 150_000, 20_000, 0.5, 1.5, seed=12)
+    k, p, eps = 8, 1.2, 1e-8
+    print(f"[case] rhvp oracle {dtype}", flush=True)
+    Uh, Vh = _tangent_pair(g.n, k, seed=3)
+    U, V = _place(Uh, Vh, dtype, "interleaved")
+    # the oracle sees exactly the rounded inputs
+    Ur, Vr = U.double().cpu().numpy(), V.double().cpu().numpy()
+    dg = gu.device_graph(g, k)
+    RH, RG, MG, Fc = pspec.rhvp(dg, U, V, p, eps)
+    HVo, Go, Fco = gu.oracle_hvp(g, Ur, Vr, p, eps)
+    RGo, MGo = orc.project(Ur, Go)
+    RHo = orc.riemannian_hessian(Ur, Go, HVo, Vr)
+    tol_g, tol_h = (1e-5, 1e-4) if dtype == torch.float32 else (1e-11, 1e-11)
+    e = dict(F=float(np.max(np.abs(Fc.cpu().numpy() - Fco) / np.abs(Fco))),
+             MG=gu.rel(MG.cpu().numpy(), MGo), RG=gu.rel(RG.double().cpu().numpy(), RGo),
+             RH=gu.rel(RH.double().cpu().numpy(), RHo))
+    print(e)
+    assert e["F"] < tol_g and e["MG"] < tol_g and e["RG"] < tol_g and e["RH"] < tol_h, e
+    # RG is tangent at U, and so is RH (for tangent V the correction term keeps it there)
+    Ut = torch.as_tensor(Ur).cuda()
+    assert float((Ut.T @ RG.double()).abs().max()) < (1e-5 if dtype == torch.float32 else 1e-12)
+
+
+def test_rhvp_rejects_bad_arguments():
+    g = gen.sbm_bernoulli(1000, 4, 0.05, 0.002)
+    dg = gu.device_graph(g, 4)
+    U = torch.randn(g.n, 4, device="cuda")
+    V = torch.randn(g.n, 4, device="cuda")
+    with pytest.raises(pspec.PSpecError):
+        pspec.rhvp(dg, U, V, 1.5, 1e-8, RH=U)  # output overlaps U
+    with pytest.raises(pspec.PSpecError):
+        pspec.rhvp(dg, U, V, 1.5, 0.0)  # eps must be positive
+    R = torch.empty_like(U)
+    with pytest.raises(pspec.PSpecError):
+        pspec.rhvp(dg, U, V, 1.5, 1e-8, RH=R, RG=R)  # outputs overlap each other
