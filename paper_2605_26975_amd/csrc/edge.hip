@@ -486,10 +486,12 @@ __device__ __forceinline__ ColScalars col_scalars(const double *__restrict__ sc,
 // Epilogue of one entry: from u_i, v_i and the raw rows L_i = (Delta_p u)_i, J_i (edge part of the
 // Hessian over p - 1), the gradient g = (p/D)(L - F phi_p(u)) and
 // HV = (p/D)((p-1) J - F (p-1) psi(u) v - g a - phi_p(u) b), both rounded to T.  Every kernel that
-// forms these entries goes through this function, so they agree bit for bit.
+// forms these entries goes through this function, so they agree bit for bit; contraction into
+// FMAs is off here, since the compiler would otherwise fuse differently in different kernels.
 template <typename T, int MODE>
 __device__ __forceinline__ void epilogue(const PowM2<T> &pw, T epsc, double p, const ColScalars &s, T u, T v, T l,
                                          T j, T &gout, T &hout) {
+#pragma clang fp contract(off)
     const T h = pw(fabs(u));
     const T phi = h * u;
     const double g = s.pD * ((double)l - s.F * (double)phi);
