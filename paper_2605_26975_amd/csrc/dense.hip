@@ -128,14 +128,14 @@ void launch_project(int64_t n, int k, const T *U, int64_t ldu, const T *Z, int64
     double *part = ws;
     double *mid = part + kDenseBlocks * kk;
     double *Mw = mid + (kDenseBlocks / kTreeFan) * kk;
-    gram_partial<T, K, VEC, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, Z, ldz, part);
+    gram_partial<T, K, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, Z, ldz, part);
     sum_partials(part, (int)kk, mid, Mw, M, s);
     if (X)
-        apply_rows<T, K, VEC, false, true, true><<<row_blocks(n), kBlock, 0, s>>>(
-            n, k, 1.0, Z, ldz, U, ldu, nullptr, 0, 0.0, Mw, -1.0, X, ldx, MX, -1.0, out, ldo);
+        launch_apply<T, K, VEC, false, true, true>(s, n, k, 1.0, Z, ldz, U, ldu, nullptr, 0, 0.0, Mw, -1.0, X, ldx, MX,
+                                                   -1.0, out, ldo);
     else
-        apply_rows<T, K, VEC, false, false, true><<<row_blocks(n), kBlock, 0, s>>>(
-            n, k, 1.0, Z, ldz, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr, 0, nullptr, 0.0, out, ldo);
+        launch_apply<T, K, VEC, false, false, true>(s, n, k, 1.0, Z, ldz, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr, 0,
+                                                    nullptr, 0.0, out, ldo);
 }
 
 template <typename T, int K>
@@ -157,11 +157,11 @@ void launch_retract(int64_t n, int k, const T *U, int64_t ldu, const T *eta, int
     double *mid = part + kDenseBlocks * kk;
     double *Mw = mid + (kDenseBlocks / kTreeFan) * kk;
     double *Rinv = Mw + kk;
-    gram_partial<T, K, VEC, true, true><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, eta, lde, t, nullptr, 0, part);
+    gram_partial<T, K, true, true><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, eta, lde, t, nullptr, 0, part);
     sum_partials(part, (int)kk, mid, Mw, nullptr, s);
     chol_inv<<<1, 64, 0, s>>>(k, Mw, R, Rinv);
-    apply_rows<T, K, VEC, true, false, false><<<row_blocks(n), kBlock, 0, s>>>(
-        n, k, 0.0, nullptr, 0, U, ldu, eta, lde, t, Rinv, 1.0, nullptr, 0, nullptr, 0.0, out, ldo);
+    launch_apply<T, K, VEC, true, false, false>(s, n, k, 0.0, nullptr, 0, U, ldu, eta, lde, t, Rinv, 1.0, nullptr, 0,
+                                                nullptr, 0.0, out, ldo);
 }
 
 template <typename T, int K>

@@ -1,7 +1,8 @@
-// Shared pieces of the dense n x k kernels: 16-byte row access, the tile geometry and the FP64
-// accumulation order of tall-skinny Gram matrices, and the fixed-order reduction of per-block
-// partials.  The Gram accumulation is used both by the stand-alone Gram kernel and by the fused
-// epilogue of the Riemannian Hessian-vector product, so the two produce identical bits.
+// Shared pieces of the dense n x k kernels: 16-byte row access, the FP64 matrix-core (MFMA)
+// accumulation of tall-skinny Gram matrices and of the row-block products X M, and the fixed-order
+// reduction of per-block partials.  The Gram accumulation and the row-block products are used both
+// by the stand-alone kernels and by the fused epilogue of the Riemannian Hessian-vector product;
+// both follow the same instruction sequence, so the two produce identical bits.
 #pragma once
 
 #include <initializer_list>
@@ -11,7 +12,6 @@
 
 namespace pspec {
 namespace {
-
 
 constexpr int kDenseBlocks = 1024;  // first-level partials of Gram matrices and dot products
 constexpr int kTreeFan = 32;         // partials summed per thread at each further level
@@ -84,37 +84,6 @@ __device__ __forceinline__ void store_row(T *p, int k, const T (&r)[K]) {
     }
 }
 
-// Rows per Gram tile: 3072 values (FP32) or 1536 (FP64) per matrix, 12 or 6 per thread, so each
-// thread keeps 48 bytes of every input in flight while the previous tile is consumed.
-template <typename T, int K>
-constexpr int gram_tile_rows() {
-    return (sizeof(T) == 4 ? 3072 : 1536) / K;
-}
-
-// Rows of the per-wave reduction buffer of a Gram accumulation (one per sub-block held by a wave).
-template <int K>
-constexpr int gram_red() {
-    return (K / 4) * (K / 4) <= 64 ? (K / 4) * (K / 4) : 64;
-}
-
-// Geometry of a Gram accumulation: thread (rg, sub) owns the 4 x 4 sub-block `sub` of the k x k
-// result and the tile rows rg, rg + RG, ...; each thread fetches PER vectors of W values per tile.
-template <typename T, int K, bool VEC>
-struct GramGeom {
-    static constexpr int NS = K / 4;
-    static constexpr int TPR = NS * NS;
-    static constexpr int RG = kBlock / TPR;
-    static constexpr int TR = gram_tile_rows<T, K>();
-    static constexpr int W = VEC ? Vec16<T>::W : 1;
-    static constexpr int CV = K / W;  // vectors per row
-    static constexpr int PER = TR * CV / kBlock;
-    static_assert(PER * kBlock == TR * CV, "tile must split evenly over the threads");
-    static_assert(kBlock % CV == 0, "a thread's columns must not change between its vectors");
-    static constexpr int NW = kBlock / 64;
-    static constexpr int RED = gram_red<K>();
-    static constexpr size_t RED_BYTES = (size_t)NW * RED * 16 * sizeof(double);
-};
-
 // Contiguous row range [r0, r1) of workgroup blockIdx.x when n rows are split over the grid.
 __device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) {
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -122,83 +91,107 @@ __device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) 
     r1 = (r0 + per < n) ? r0 + per : n;
 }
 
-// W values of one row starting at column c: one 16-byte vector when VEC, else column c alone
-// (zero when c >= k).
-template <typename T, int W, bool VEC>
-__device__ __forceinline__ void load_cols(const T *row, int c, int k, T (&x)[W]) {
-    if constexpr (VEC) {
-        using V = typename Vec16<T>::type;
-        static_assert(W == Vec16<T>::W, "vector width");
-        const V v = *reinterpret_cast<const V *>(row + c);
-        __builtin_memcpy(x, &v, sizeof(V));
-    } else {
-        static_assert(W == 1, "scalar width");
-        x[0] = c < k ? row[c] : T(0);
+// Guarded loads read an in-range element (row and column clamped) and are masked only after every
+// load of the batch has been issued: a load whose value is selected right away is turned into a
+// load under a branch and waited for on the spot, which serialises the loads of a wave.  pin()
+// marks the point where the batch's values are first needed (an empty asm statement that reads
+// and writes the register, so the loads cannot be moved below it); it emits no instruction.
+__device__ __forceinline__ int64_t clamp_index(int64_t i, int64_t n) { return i < n ? i : n - 1; }
+
+template <typename T>
+__device__ __forceinline__ T clamped_load(const T *base, int64_t ld, int64_t row, int64_t n, int col, int k) {
+    return base[clamp_index(row, n) * ld + (col < k ? col : k - 1)];
+}
+
+template <typename T>
+__device__ __forceinline__ void pin(T &x) {
+    __asm__ volatile("" : "+v"(x));
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void pin_all(T (&x)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) pin(x[i]);
+}
+
+// ---- FP64 matrix cores ------------------------------------------------------------------------
+// v_mfma_f64_16x16x4f64 computes D = A B + C for A 16 x 4, B 4 x 16 and C, D 16 x 16.  Lane l
+// (l = 16 q + c, q < 4, c < 16) supplies A[c][q] and B[q][c] and holds D[4 i + q][c] in element i of
+// its accumulator.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma_f64(double a, double b, dbl4 acc) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+// Columns are handled in 16-wide tiles; k < 16 is padded with zero columns.
+template <int K>
+constexpr int mf_tiles() {
+    return K < 16 ? 1 : K / 16;
+}
+
+// ---- Gram matrices M = A^T B -----------------------------------------------------------------
+// The rows [r0, r1) of a workgroup are taken in groups of four; wave w takes the groups w, w + 4,
+// w + 8, ... in that order and feeds group g to one MFMA per pair of column tiles, lane (q, c)
+// supplying row 4 g + q, column 16 t + c of both factors.  For UG groups at a time,
+// load(row, c, raw) issues the clamped loads of one group into raw, raw.pin() follows all of them,
+// and finish(row, c, raw, a, b) forms the left factor a[t] and the NB right factors b[m][t] at
+// (row, 16 t + c), zero outside the range or past column k.
+template <typename T, int K, int NB, int UG, typename Raw, typename Load, typename Finish>
+__device__ __forceinline__ void gram_mfma_rows(int64_t r0, int64_t r1, Load &&load, Finish &&finish,
+                                               dbl4 (&acc)[NB][mf_tiles<K>()][mf_tiles<K>()]) {
+    constexpr int CT = mf_tiles<K>();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane >> 4, c = lane & 15;
+    for (int64_t base = r0 + 4 * w; base < r1; base += (int64_t)16 * UG) {
+        Raw raw[UG];
+#pragma unroll
+        for (int u = 0; u < UG; ++u) load(base + 16 * u + q, c, raw[u]);
+#pragma unroll
+        for (int u = 0; u < UG; ++u) raw[u].pin();
+        T a[UG][CT], b[UG][NB][CT];
+#pragma unroll
+        for (int u = 0; u < UG; ++u) finish(base + 16 * u + q, c, raw[u], a[u], b[u]);
+#pragma unroll
+        for (int u = 0; u < UG; ++u)
+#pragma unroll
+            for (int m = 0; m < NB; ++m)
+#pragma unroll
+                for (int ta = 0; ta < CT; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < CT; ++tb)
+                        acc[m][ta][tb] = mfma_f64((double)a[u][ta], (double)b[u][m][tb], acc[m][ta][tb]);
     }
 }
 
-// acc[m] += A^T B_m over the rows rg, rg + RG, ... of one LDS tile of TR rows (NB = 1 or 2 right
-// factors sharing the left one).  Each matrix is accumulated in the same order whatever NB is.
-template <typename T, int K, int TR, int NB>
-__device__ __forceinline__ void gram_tile(const T (*sA)[K], const T (*sB0)[K], const T (*sB1)[K], int rg, int a0,
-                                          int b0, double (&acc)[NB][4][4]) {
-    constexpr int RG = kBlock / ((K / 4) * (K / 4));
-    for (int r = rg; r < TR; r += RG) {
-        double av[4], bv[NB][4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            av[q] = (double)sA[r][a0 + q];
-            bv[0][q] = (double)sB0[r][b0 + q];
-            if constexpr (NB > 1) bv[1][q] = (double)sB1[r][b0 + q];
-        }
-#pragma unroll
-        for (int m = 0; m < NB; ++m)
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[m][p][q] = fma(av[p], bv[m][q], acc[m][p][q]);
-    }
-}
-
-// Sum the row groups of acc[m] (inside a wave with shuffles, across waves through LDS, in a fixed
-// order) and write the block's partials part[m][a][b] (a, b < k).  s_red may alias the tiles: the
-// caller has passed a barrier after its last tile.
+// Add the four waves' tiles in wave order and write the block's partials part[m][a][b] (a, b < k).
 template <int K, int NB>
-__device__ __forceinline__ void gram_block_reduce(double (&acc)[NB][4][4], double (*s_red)[gram_red<K>()][16], int k, double *__restrict__ part) {
-    constexpr int TPR = (K / 4) * (K / 4);
-    constexpr int NW = kBlock / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int sub = tid % TPR, a0 = (sub / (K / 4)) * 4, b0 = (sub % (K / 4)) * 4;
+__device__ __forceinline__ void gram_mfma_reduce(dbl4 (&acc)[NB][mf_tiles<K>()][mf_tiles<K>()],
+                                                 double (*s_red)[4][64], int k, double *__restrict__ part) {
+    constexpr int CT = mf_tiles<K>();
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const size_t kk = (size_t)k * k;
 #pragma unroll
-    for (int m = 0; m < NB; ++m) {
+    for (int m = 0; m < NB; ++m)
 #pragma unroll
-        for (int o = TPR; o < 64; o <<= 1)
+        for (int ta = 0; ta < CT; ++ta)
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
+            for (int tb = 0; tb < CT; ++tb) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[m][p][q] += __shfl_xor(acc[m][p][q], o);
-        if (lane < (TPR <= 64 ? TPR : 64))
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) s_red[wave][lane][p * 4 + q] = acc[m][p][q];
-        __syncthreads();
-        if (tid < TPR) {
-            const int wl = TPR <= 64 ? tid : tid % 64;
-            for (int e = 0; e < 16; ++e) {
-                double v = 0.0;
-                if (TPR <= 64) {  // every wave holds all TPR sub-blocks: add the waves in order
-                    for (int w = 0; w < NW; ++w) v += s_red[w][wl][e];
-                } else {  // one row group: sub-block tid lives in wave tid / 64
-                    v = s_red[tid / 64][wl][e];
-                }
-                const int a = a0 + e / 4, b = b0 + e % 4;
-                if (a < k && b < k) part[m * kk + a * k + b] = v;
+                for (int i = 0; i < 4; ++i) s_red[w][i][lane] = acc[m][ta][tb][i];
+                __syncthreads();
+                const int i = tid >> 6;  // element i of lane `lane` of every wave
+                const double v = ((s_red[0][i][lane] + s_red[1][i][lane]) + s_red[2][i][lane]) + s_red[3][i][lane];
+                const int a = 16 * ta + 4 * i + (lane >> 4), b = 16 * tb + (lane & 15);
+                if (a < k && b < k) part[m * kk + (size_t)a * k + b] = v;
+                __syncthreads();
             }
-        }
-        __syncthreads();
-    }
+}
+
+// Rows gathered per wave before their products are issued.
+template <int NB>
+constexpr int gram_groups() {
+    return 8;
 }
 
 // One level of a fixed-order reduction over the partials part[q][e] (row stride `stride`):
@@ -233,83 +226,142 @@ inline void sum_partials(const double *part, int len, double *mid, double *out, 
     sum_level<<<dim3(gx, 1), kBlock, 0, s>>>(mid, ngroups, len, len, out, out2);
 }
 
-// Entry (a, c) of a k x k row-major matrix held in global memory, read at a wave-uniform address.
-// With VEC (k == K) the offset is a compile-time constant after unrolling, so the load is a scalar
-// load into SGPRs; otherwise entries outside k x k read as zero.
-template <int K, bool VEC>
-__device__ __forceinline__ double mat_at(const double *__restrict__ M, int k, int a, int c) {
-    if constexpr (VEC) return M[a * K + c];
-    return (a < k && c < k) ? M[a * k + c] : 0.0;
+// The k x k matrix operands of the lane-per-row kernels are read as M[r * K + c] at compile-time
+// offsets and wave-uniform addresses.  With VEC (k == K) M is the caller's matrix in global memory,
+// so the reads become scalar loads into SGPR operands; otherwise it is first copied, zero-padded to
+// K x K, into LDS (runtime offsets k * r + c would defeat the scalar path) and read as broadcasts.
+template <int K>
+__device__ __forceinline__ void stage_matrix(const double *__restrict__ M, int k, double *sM) {
+    for (int e = threadIdx.x; e < K * K; e += kBlock) {
+        const int a = e / K, c = e % K;
+        sM[e] = (a < k && c < k) ? M[a * k + c] : 0.0;
+    }
 }
 
-// Per-block partial of M = A^T B over a contiguous row range.  A = A1 + t A2 (rounded to T) when
-// AXPY; B = A when SAME.  Tiles of rows are staged in LDS with coalesced (16-byte when VEC) loads, the
-// next tile being fetched into registers while the current one is consumed.  The LDS of the tiles
-// is reused for the final reduction over row groups.
-template <typename T, int K, bool VEC, bool AXPY, bool SAME>
+// Per-block partial of M = A^T B over a contiguous row range, on the FP64 matrix cores.
+// A = A1 + t A2 (rounded to T) when AXPY; B = A when SAME.
+template <typename T, int K, bool AXPY, bool SAME>
 __global__ __launch_bounds__(kBlock) void gram_partial(int64_t n, int k, const T *__restrict__ A1, int64_t lda1,
                                                      const T *__restrict__ A2, int64_t lda2, double t,
                                                      const T *__restrict__ B, int64_t ldb, double *__restrict__ part) {
-    using Geo = GramGeom<T, K, VEC>;
-    constexpr int TR = Geo::TR, W = Geo::W, CV = Geo::CV, PER = Geo::PER;
-    constexpr size_t TILE_BYTES = (size_t)TR * K * sizeof(T) * (SAME ? 1 : 2);
-    __shared__ __align__(16) unsigned char smem[TILE_BYTES > Geo::RED_BYTES ? TILE_BYTES : Geo::RED_BYTES];
-    T(*sA)[K] = reinterpret_cast<T(*)[K]>(smem);
-    T(*sB)[K] = SAME ? sA : reinterpret_cast<T(*)[K]>(smem + (size_t)TR * K * sizeof(T));
-    const int tid = threadIdx.x, sub = tid % Geo::TPR, rg = tid / Geo::TPR;
-    const int a0 = (sub / Geo::NS) * 4, b0 = (sub % Geo::NS) * 4;
-    const int c = (tid % CV) * W;  // this thread's columns, the same for all its vectors
+    constexpr int CT = mf_tiles<K>();
+    __shared__ double s_red[4][4][64];
     int64_t r0, r1;
     block_rows(n, r0, r1);
-    double acc[1][4][4];
+    dbl4 acc[1][CT][CT];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int ta = 0; ta < CT; ++ta)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[0][p][q] = 0.0;
-    T xa[PER][W], xb[SAME ? 1 : PER][W];
-    auto fetch = [&](int64_t t0) {
-#pragma unroll
-        for (int v = 0; v < PER; ++v) {
-            const int64_t i = t0 + (tid + v * kBlock) / CV;
-            T x[W], x2[W], y[W];
-#pragma unroll
-            for (int q = 0; q < W; ++q) x[q] = x2[q] = y[q] = T(0);
-            if (i < r1) {
-                load_cols<T, W, VEC>(A1 + i * lda1, c, k, x);
-                if constexpr (AXPY) load_cols<T, W, VEC>(A2 + i * lda2, c, k, x2);
-                if constexpr (!SAME) load_cols<T, W, VEC>(B + i * ldb, c, k, y);
-            }
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                xa[v][q] = AXPY ? (T)((double)x[q] + t * (double)x2[q]) : x[q];
-                if constexpr (!SAME) xb[v][q] = y[q];
-            }
+        for (int tb = 0; tb < CT; ++tb) acc[0][ta][tb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    struct Raw {
+        T x[CT], x2[AXPY ? CT : 1], y[SAME ? 1 : CT];
+        __device__ void pin() {
+            pin_all(x);
+            if constexpr (AXPY) pin_all(x2);
+            if constexpr (!SAME) pin_all(y);
         }
     };
-    if (r0 < r1) fetch(r0);
-    for (int64_t t0 = r0; t0 < r1; t0 += TR) {
+    auto load = [&](int64_t row, int c, Raw &raw) {
 #pragma unroll
-        for (int v = 0; v < PER; ++v) {
-            const int r = (tid + v * kBlock) / CV;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                sA[r][c + q] = xa[v][q];
-                if constexpr (!SAME) sB[r][c + q] = xb[v][q];
-            }
+        for (int ti = 0; ti < CT; ++ti) {
+            raw.x[ti] = clamped_load(A1, lda1, row, r1, 16 * ti + c, k);
+            if constexpr (AXPY) raw.x2[ti] = clamped_load(A2, lda2, row, r1, 16 * ti + c, k);
+            if constexpr (!SAME) raw.y[ti] = clamped_load(B, ldb, row, r1, 16 * ti + c, k);
         }
-        __syncthreads();
-        if (t0 + TR < r1) fetch(t0 + TR);
-        gram_tile<T, K, TR, 1>(sA, sB, nullptr, rg, a0, b0, acc);
-        __syncthreads();
-    }
-    gram_block_reduce<K, 1>(acc, reinterpret_cast<double(*)[gram_red<K>()][16]>(smem), k,
-                            part + (int64_t)blockIdx.x * k * k);
+    };
+    auto finish = [&](int64_t row, int c, const Raw &raw, T(&a)[CT], T(&b)[1][CT]) {
+#pragma unroll
+        for (int ti = 0; ti < CT; ++ti) {
+            const bool ok = row < r1 && 16 * ti + c < k;
+            T x = raw.x[ti];
+            if constexpr (AXPY) x = (T)((double)x + t * (double)raw.x2[ti]);
+            a[ti] = ok ? x : T(0);
+            if constexpr (SAME) b[0][ti] = a[ti];
+            else b[0][ti] = ok ? raw.y[ti] : T(0);
+        }
+    };
+    gram_mfma_rows<T, K, 1, gram_groups<1>(), Raw>(r0, r1, load, finish, acc);
+    gram_mfma_reduce<K, 1>(acc, s_red, k, part + (int64_t)blockIdx.x * k * k);
 }
 
-// out[i, :] = beta Z[i, :] + (s1 (A1[i, :] + t A2[i, :])) M1 + (s2 X[i, :]) M2, with A1 + t A2
-// rounded to T first.  One lane per row: the row's k outputs are accumulated in FP64 registers; the
-// row-vector terms are added in the order A, X, Z so that the products can start while the later
-// loads are still in flight.  s1 and s2 scale the row values (exact for the +-1 the library uses).
+// ---- Row-block products out = beta Z + (s1 A) M1 + (s2 X) M2 ------------------------------------
+// Each wave computes 16-row tiles, one 16-column tile of the output per MFMA chain.  The k index of
+// the products is permuted so that lane (q, c) needs the contiguous chunk k/4 q .. k/4 q + k/4 - 1 of
+// row c of the tile (one or two 16-byte loads): step s of a chain takes k-index kperm(s, q) =
+// KS q + s from every lane.  Lane (q, c) then holds output row 4 i + q, column 16 t + c.
+template <int K>
+constexpr int mf_steps() {
+    return (K < 16 ? 16 : K) / 4;  // KS: MFMA steps per chain (padded width / 4)
+}
+
+// The M operand of lane (q, c): M[KS q + s][16 t + c] for every tile t and step s (zero past k).
+template <int K>
+__device__ __forceinline__ void load_mf_operand(const double *__restrict__ M, int k, double (&mb)[mf_tiles<K>()][mf_steps<K>()]) {
+    constexpr int KS = mf_steps<K>();
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+#pragma unroll
+    for (int t = 0; t < mf_tiles<K>(); ++t)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int r = KS * q + s, col = 16 * t + c;
+            mb[t][s] = (r < k && col < k) ? M[r * k + col] : 0.0;
+        }
+}
+
+// The A-operand chunk of lane (q, c): row `row`, columns KS q .. KS q + KS - 1, loaded clamped into
+// the valid range (one or two 16-byte loads when VEC); mask_mf_chunk zeroes it past k or n once the
+// batch's loads are issued and pinned.
+template <typename T, int K, bool VEC>
+__device__ __forceinline__ void load_mf_chunk(const T *base, int64_t ld, int64_t row, int64_t n, int k,
+                                              T (&x)[mf_steps<K>()]) {
+    constexpr int KS = mf_steps<K>();
+    const int c0 = KS * ((threadIdx.x & 63) >> 4);
+    if constexpr (VEC) {
+        using V = typename Vec16<T>::type;
+        constexpr int W = Vec16<T>::W;
+        const T *src = base + clamp_index(row, n) * ld + (c0 < K ? c0 : 0);
+#pragma unroll
+        for (int m = 0; m < KS / W; ++m) {
+            const V v = *reinterpret_cast<const V *>(src + m * W);
+            __builtin_memcpy(&x[m * W], &v, sizeof(V));
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) x[s] = clamped_load(base, ld, row, n, c0 + s, k);
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void mask_mf_chunk(int64_t row, int64_t n, int k, T (&x)[mf_steps<K>()]) {
+    constexpr int KS = mf_steps<K>();
+    const int c0 = KS * ((threadIdx.x & 63) >> 4);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) x[s] = (row < n && c0 + s < k) ? x[s] : T(0);
+}
+
+// acc[t] += (sc x) M for the chunk x of this lane's row (one chain of KS MFMAs per column tile).
+template <typename T, int K>
+__device__ __forceinline__ void mf_products(const T (&x)[mf_steps<K>()], double sc,
+                                            const double (&mb)[mf_tiles<K>()][mf_steps<K>()],
+                                            dbl4 (&acc)[mf_tiles<K>()]) {
+#pragma unroll
+    for (int t = 0; t < mf_tiles<K>(); ++t)
+#pragma unroll
+        for (int s = 0; s < mf_steps<K>(); ++s) acc[t] = mfma_f64(sc * (double)x[s], mb[t][s], acc[t]);
+}
+
+// Tiles of 16 rows handed to the waves of the grid in turn, MF_TPI per wave and iteration.
+constexpr int MF_TPI = 2;
+__device__ __forceinline__ int64_t mf_first_tile() { return (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); }
+__device__ __forceinline__ int64_t mf_tile_stride() { return (int64_t)gridDim.x * (kBlock / 64); }
+inline unsigned mf_grid(int64_t n) {
+    const int64_t tiles = (n + 15) / 16, blocks = (tiles + kBlock / 64 - 1) / (kBlock / 64);
+    return (unsigned)(blocks < 4096 ? (blocks < 1 ? 1 : blocks) : 4096);
+}
+
+// out = beta Z + (s1 (A1 + t A2)) M1 + (s2 X) M2 with A1 + t A2 rounded to T first, on the FP64
+// matrix cores (k <= 32; wider blocks use apply_rows_wide).  s1 and s2 scale the row values (exact for
+// the +-1 the library uses).  VEC: 16-byte chunk loads (k == K and aligned rows).
 template <typename T, int K, bool VEC, bool AXPY, bool HAS_X, bool HAS_Z>
 __global__ __launch_bounds__(kBlock) void apply_rows(int64_t n, int k, double beta, const T *__restrict__ Z,
                                                    int64_t ldz, const T *__restrict__ A1, int64_t lda1,
@@ -318,6 +370,85 @@ __global__ __launch_bounds__(kBlock) void apply_rows(int64_t n, int k, double be
                                                    const T *__restrict__ X, int64_t ldx,
                                                    const double *__restrict__ M2, double s2, T *__restrict__ out,
                                                    int64_t ldo) {
+    constexpr int CT = mf_tiles<K>(), KS = mf_steps<K>();
+    static_assert(K <= 32, "wide blocks use apply_rows_wide");
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    double m1[CT][KS], m2[HAS_X ? CT : 1][HAS_X ? KS : 1];
+    load_mf_operand<K>(M1, k, m1);
+    if constexpr (HAS_X) load_mf_operand<K>(M2, k, m2);
+    // each wave takes MF_TPI tiles per iteration (tile, tile + stride, ...) to keep more loads in flight
+    const int64_t stride = mf_tile_stride();
+    for (int64_t tile0 = mf_first_tile(); tile0 * 16 < n; tile0 += MF_TPI * stride) {
+        T a[MF_TPI][KS], a2[MF_TPI][AXPY ? KS : 1], x[MF_TPI][HAS_X ? KS : 1], z[MF_TPI][HAS_Z ? CT : 1][4];
+#pragma unroll
+        for (int j = 0; j < MF_TPI; ++j) {
+            const int64_t row0 = (tile0 + j * stride) * 16;
+            load_mf_chunk<T, K, VEC>(A1, lda1, row0 + c, n, k, a[j]);
+            if constexpr (AXPY) load_mf_chunk<T, K, VEC>(A2, lda2, row0 + c, n, k, a2[j]);
+            if constexpr (HAS_X) load_mf_chunk<T, K, VEC>(X, ldx, row0 + c, n, k, x[j]);
+            if constexpr (HAS_Z)
+#pragma unroll
+                for (int ti = 0; ti < CT; ++ti)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        z[j][ti][i] = clamped_load(Z, ldz, row0 + 4 * i + q, n, 16 * ti + c, k);
+        }
+#pragma unroll
+        for (int j = 0; j < MF_TPI; ++j) {
+            pin_all(a[j]);
+            if constexpr (AXPY) pin_all(a2[j]);
+            if constexpr (HAS_X) pin_all(x[j]);
+            if constexpr (HAS_Z)
+#pragma unroll
+                for (int ti = 0; ti < CT; ++ti) pin_all(z[j][ti]);
+        }
+#pragma unroll
+        for (int j = 0; j < MF_TPI; ++j) {
+            const int64_t row0 = (tile0 + j * stride) * 16;
+            mask_mf_chunk<T, K>(row0 + c, n, k, a[j]);
+            if constexpr (AXPY) mask_mf_chunk<T, K>(row0 + c, n, k, a2[j]);
+            if constexpr (HAS_X) mask_mf_chunk<T, K>(row0 + c, n, k, x[j]);
+            if constexpr (AXPY)
+#pragma unroll
+                for (int s = 0; s < KS; ++s) a[j][s] = (T)((double)a[j][s] + t * (double)a2[j][s]);
+            dbl4 acc[CT];
+#pragma unroll
+            for (int ti = 0; ti < CT; ++ti) acc[ti] = dbl4{0.0, 0.0, 0.0, 0.0};
+            mf_products<T, K>(a[j], s1, m1, acc);
+            if constexpr (HAS_X) mf_products<T, K>(x[j], s2, m2, acc);
+#pragma unroll
+            for (int ti = 0; ti < CT; ++ti)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t r = row0 + 4 * i + q;
+                    const int col = 16 * ti + c;
+                    // z is only used where (r, col) is in range, so it needs no mask
+                    if (r < n && col < k)
+                        out[r * ldo + col] = (T)(HAS_Z ? fma(beta, (double)z[j][ti][i], acc[ti][i]) : acc[ti][i]);
+                }
+        }
+    }
+}
+
+// Apply for k > 32 (see apply_rows): one lane per row on the FP64 VALU; the row's k outputs are
+// accumulated in registers in the order A, X, Z so that the products can start while the later
+// loads are still in flight.
+template <typename T, int K, bool VEC, bool AXPY, bool HAS_X, bool HAS_Z>
+__global__ __launch_bounds__(kBlock) void apply_rows_wide(int64_t n, int k, double beta, const T *__restrict__ Z,
+                                                   int64_t ldz, const T *__restrict__ A1, int64_t lda1,
+                                                   const T *__restrict__ A2, int64_t lda2, double t,
+                                                   const double *__restrict__ M1, double s1,
+                                                   const T *__restrict__ X, int64_t ldx,
+                                                   const double *__restrict__ M2, double s2, T *__restrict__ out,
+                                                   int64_t ldo) {
+    __shared__ double sM1[VEC ? 1 : K * K], sM2[VEC || !HAS_X ? 1 : K * K];
+    if constexpr (!VEC) {
+        stage_matrix<K>(M1, k, sM1);
+        if constexpr (HAS_X) stage_matrix<K>(M2, k, sM2);
+        __syncthreads();
+        M1 = sM1;
+        M2 = sM2;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     T a[K], a2[AXPY ? K : 1], x[HAS_X ? K : 1], z[HAS_Z ? K : 1];
@@ -329,24 +460,39 @@ __global__ __launch_bounds__(kBlock) void apply_rows(int64_t n, int k, double be
     double o[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) o[c] = 0.0;
-#pragma unroll
+#pragma unroll(VEC ? K : 1)
     for (int r = 0; r < K; ++r) {
         const double av = s1 * (AXPY ? (double)(T)((double)a[r] + t * (double)a2[r]) : (double)a[r]);
 #pragma unroll
-        for (int c = 0; c < K; ++c) o[c] = fma(av, mat_at<K, VEC>(M1, k, r, c), o[c]);
+        for (int c = 0; c < K; ++c) o[c] = fma(av, M1[r * K + c], o[c]);
     }
     if constexpr (HAS_X) {
-#pragma unroll
+#pragma unroll(VEC ? K : 1)
         for (int r = 0; r < K; ++r) {
             const double xv = s2 * (double)x[r];
 #pragma unroll
-            for (int c = 0; c < K; ++c) o[c] = fma(xv, mat_at<K, VEC>(M2, k, r, c), o[c]);
+            for (int c = 0; c < K; ++c) o[c] = fma(xv, M2[r * K + c], o[c]);
         }
     }
     T res[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) res[c] = (T)(HAS_Z ? fma(beta, (double)z[c], o[c]) : o[c]);
     store_row<T, K, VEC>(out + i * ldo, k, res);
+}
+
+// Launch of the row-block product on stream s (matrix cores for k <= 32, apply_rows_wide above).
+template <typename T, int K, bool VEC, bool AXPY, bool HAS_X, bool HAS_Z>
+void launch_apply(hipStream_t s, int64_t n, int k, double beta, const T *Z, int64_t ldz, const T *A1, int64_t lda1,
+                  const T *A2, int64_t lda2, double t, const double *M1, double s1, const T *X, int64_t ldx,
+                  const double *M2, double s2, T *out, int64_t ldo) {
+    if constexpr (K <= 32) {
+        apply_rows<T, K, VEC, AXPY, HAS_X, HAS_Z><<<mf_grid(n), kBlock, 0, s>>>(n, k, beta, Z, ldz, A1, lda1, A2, lda2, t,
+                                                                            M1, s1, X, ldx, M2, s2, out, ldo);
+    } else {
+        const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+        apply_rows_wide<T, K, VEC, AXPY, HAS_X, HAS_Z><<<blocks, kBlock, 0, s>>>(n, k, beta, Z, ldz, A1, lda1, A2, lda2,
+                                                                               t, M1, s1, X, ldx, M2, s2, out, ldo);
+    }
 }
 
 }  // namespace

@@ -525,134 +525,155 @@ __global__ __launch_bounds__(kBlock) void finalize(int64_t n, int k, const T *__
 }
 
 // Fused epilogue and Gram matrices of the Riemannian Hessian-vector product: per workgroup (a fixed
-// grid of kDenseBlocks, each over a contiguous row range) the FP64 partials of U^T G and U^T HV,
-// with G and HV formed from the raw rows L, J by the epilogue above and kept in LDS only.  The row
-// ranges, tiles and accumulation order are those of the stand-alone Gram kernel, so the sums equal
-// the Gram matrices of the finalized G and HV bit for bit.
-template <typename T, int K, bool VEC>
+// grid of kDenseBlocks, each over a contiguous row range) the FP64 partials of U^T G and U^T HV on
+// the matrix cores, with G and HV formed from the raw rows L, J by the epilogue above and never
+// stored.  Rows, groups and the MFMA sequence are those of the stand-alone Gram kernel, so the sums
+// equal the Gram matrices of the finalized G and HV bit for bit.
+template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void finalize_gram(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
                                                       const T *__restrict__ V, int64_t ldv, const T *__restrict__ L,
                                                       int64_t ldl, const T *__restrict__ J, int64_t ldj, PowM2<T> pw,
                                                       T epsc, double p, const double *__restrict__ sc, int k_max,
                                                       double *__restrict__ part) {
-    using Geo = GramGeom<T, K, VEC>;
-    constexpr int TR = Geo::TR, W = Geo::W, CV = Geo::CV, PER = Geo::PER;
-    constexpr size_t TILE_BYTES = (size_t)TR * K * sizeof(T) * 3;
-    __shared__ __align__(16) unsigned char smem[TILE_BYTES > Geo::RED_BYTES ? TILE_BYTES : Geo::RED_BYTES];
-    T(*sU)[K] = reinterpret_cast<T(*)[K]>(smem);
-    T(*sG)[K] = reinterpret_cast<T(*)[K]>(smem + (size_t)TR * K * sizeof(T));
-    T(*sH)[K] = reinterpret_cast<T(*)[K]>(smem + 2 * (size_t)TR * K * sizeof(T));
-    const int tid = threadIdx.x, sub = tid % Geo::TPR, rg = tid / Geo::TPR;
-    const int a0 = (sub / Geo::NS) * 4, b0 = (sub % Geo::NS) * 4;
-    const int c = (tid % CV) * W;  // this thread's columns, the same for all its vectors
-    ColScalars cs[W];
+    constexpr int CT = mf_tiles<K>();
+    __shared__ double s_red[4][4][64];
+    const int c = threadIdx.x & 15;
+    ColScalars cs[CT];  // this lane's columns 16 t + c
 #pragma unroll
-    for (int q = 0; q < W; ++q) cs[q] = c + q < k ? col_scalars(sc, k_max, c + q) : ColScalars{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < CT; ++t)
+        cs[t] = 16 * t + c < k ? col_scalars(sc, k_max, 16 * t + c) : ColScalars{0.0, 0.0, 0.0, 0.0};
     int64_t r0, r1;
     block_rows(n, r0, r1);
-    double acc[2][4][4];
+    dbl4 acc[2][CT][CT];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int p2 = 0; p2 < 4; ++p2)
+        for (int ta = 0; ta < CT; ++ta)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[m][p2][q] = 0.0;
-    T xu[PER][W], xv[PER][W], xl[PER][W], xj[PER][W];
-    auto fetch = [&](int64_t t0) {
-#pragma unroll
-        for (int v = 0; v < PER; ++v) {
-            const int64_t i = t0 + (tid + v * kBlock) / CV;
-#pragma unroll
-            for (int q = 0; q < W; ++q) xu[v][q] = xv[v][q] = xl[v][q] = xj[v][q] = T(0);
-            if (i < r1) {
-                load_cols<T, W, VEC>(U + i * ldu, c, k, xu[v]);
-                load_cols<T, W, VEC>(V + i * ldv, c, k, xv[v]);
-                load_cols<T, W, VEC>(L + i * ldl, c, k, xl[v]);
-                load_cols<T, W, VEC>(J + i * ldj, c, k, xj[v]);
-            }
+            for (int tb = 0; tb < CT; ++tb) acc[m][ta][tb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    struct Raw {
+        T u[CT], v[CT], l[CT], j[CT];
+        __device__ void pin() {
+            pin_all(u);
+            pin_all(v);
+            pin_all(l);
+            pin_all(j);
         }
     };
-    if (r0 < r1) fetch(r0);
-    for (int64_t t0 = r0; t0 < r1; t0 += TR) {
+    auto load = [&](int64_t row, int cl, Raw &raw) {
 #pragma unroll
-        for (int v = 0; v < PER; ++v) {
-            const int r = (tid + v * kBlock) / CV;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                T g, hv;
-                epilogue<T, HVP>(pw, epsc, p, cs[q], xu[v][q], xv[v][q], xl[v][q], xj[v][q], g, hv);
-                // rows past the range and padded columns stay zero, as in the stand-alone Gram
-                const bool live = t0 + r < r1 && c + q < k;
-                sU[r][c + q] = xu[v][q];
-                sG[r][c + q] = live ? g : T(0);
-                sH[r][c + q] = live ? hv : T(0);
-            }
+        for (int t = 0; t < CT; ++t) {
+            const int col = 16 * t + cl;
+            raw.u[t] = clamped_load(U, ldu, row, r1, col, k);
+            raw.v[t] = clamped_load(V, ldv, row, r1, col, k);
+            raw.l[t] = clamped_load(L, ldl, row, r1, col, k);
+            raw.j[t] = clamped_load(J, ldj, row, r1, col, k);
         }
-        __syncthreads();
-        if (t0 + TR < r1) fetch(t0 + TR);
-        gram_tile<T, K, TR, 2>(sU, sG, sH, rg, a0, b0, acc);
-        __syncthreads();
-    }
-    gram_block_reduce<K, 2>(acc, reinterpret_cast<double(*)[gram_red<K>()][16]>(smem), k,
-                            part + (int64_t)blockIdx.x * 2 * k * k);
+    };
+    auto finish = [&](int64_t row, int cl, const Raw &raw, T(&a)[CT], T(&b)[2][CT]) {
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            const bool ok = row < r1 && 16 * t + cl < k;
+            T g, hv;
+            epilogue<T, HVP>(pw, epsc, p, cs[t], raw.u[t], raw.v[t], raw.l[t], raw.j[t], g, hv);
+            a[t] = ok ? raw.u[t] : T(0);
+            b[0][t] = ok ? g : T(0);
+            b[1][t] = ok ? hv : T(0);
+        }
+    };
+    gram_mfma_rows<T, K, 2, gram_groups<2>(), Raw>(r0, r1, load, finish, acc);
+    gram_mfma_reduce<K, 2>(acc, s_red, k, part + (int64_t)blockIdx.x * 2 * k * k);
 }
 
-// Projection of the fused Riemannian Hessian-vector product, one lane per row:
-//   RG_i = G_i - U_i MG,   RH_i = HV_i - U_i MH - V_i MG,   MG = U^T G, MH = U^T HV,
-// with G_i and HV_i formed again from the raw rows (held in RG and RH on entry, overwritten in
-// place) by the shared epilogue.  The products run in the order of the stand-alone projection.
+// Projection of the fused Riemannian Hessian-vector product on the matrix cores:
+//   RG = G - U MG,   RH = HV - U MH - V MG,   MG = U^T G, MH = U^T HV,
+// with G and HV formed again from the raw rows (held in RG and RH on entry, overwritten in place) by
+// the shared epilogue.  The products follow the MFMA sequence of the stand-alone projection (U then
+// V, each in k order), so the outputs equal pspec_project's bit for bit.
 template <typename T, int K, bool VEC>
 __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
                                                    const T *__restrict__ V, int64_t ldv, T *__restrict__ RG,
                                                    int64_t ldrg, T *__restrict__ RH, int64_t ldrh, PowM2<T> pw, T epsc,
                                                    double p, const double *__restrict__ sc, int k_max,
                                                    const double *__restrict__ MG, const double *__restrict__ MH) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    T u[K], v[K], g[K], hv[K];
-    load_row<T, K, VEC>(U + i * ldu, k, u);
-    load_row<T, K, VEC>(V + i * ldv, k, v);
-    load_row<T, K, VEC>(RG + i * ldrg, k, g);
-    load_row<T, K, VEC>(RH + i * ldrh, k, hv);
-    __builtin_amdgcn_sched_barrier(0);
+    constexpr int CT = mf_tiles<K>(), KS = mf_steps<K>();
+    const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+    double mg[CT][KS], mh[CT][KS];
+    load_mf_operand<K>(MG, k, mg);
+    load_mf_operand<K>(MH, k, mh);
+    ColScalars cs[CT];  // this lane's output columns 16 t + c
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
-        const ColScalars cs = c < k ? col_scalars(sc, k_max, c) : ColScalars{0.0, 0.0, 0.0, 0.0};
-        epilogue<T, HVP>(pw, epsc, p, cs, u[c], v[c], g[c], hv[c], g[c], hv[c]);
-    }
-    T res[K];
-    {
-        double o[K];
+    for (int t = 0; t < CT; ++t)
+        cs[t] = 16 * t + c < k ? col_scalars(sc, k_max, 16 * t + c) : ColScalars{0.0, 0.0, 0.0, 0.0};
+    constexpr int TPI = 1;  // one tile per iteration: this kernel already holds four rows per lane
+    const int64_t stride = mf_tile_stride();
+    for (int64_t tile0 = mf_first_tile(); tile0 * 16 < n; tile0 += TPI * stride) {
+        T ua[TPI][KS], va[TPI][KS];  // operand chunks of row row0 + c
+        T u[TPI][CT][4], v[TPI][CT][4], l[TPI][CT][4], j[TPI][CT][4];  // (row0 + 4 i + q, 16 t + c)
 #pragma unroll
-        for (int c = 0; c < K; ++c) o[c] = 0.0;
+        for (int s = 0; s < TPI; ++s) {
+            const int64_t row0 = (tile0 + s * stride) * 16;
+            load_mf_chunk<T, K, VEC>(U, ldu, row0 + c, n, k, ua[s]);
+            load_mf_chunk<T, K, VEC>(V, ldv, row0 + c, n, k, va[s]);
 #pragma unroll
-        for (int r = 0; r < K; ++r) {
-            const double ur = -1.0 * (double)u[r];
+            for (int t = 0; t < CT; ++t)
 #pragma unroll
-            for (int c = 0; c < K; ++c) o[c] = fma(ur, mat_at<K, VEC>(MG, k, r, c), o[c]);
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t r = row0 + 4 * i + q;
+                    const int col = 16 * t + c;
+                    u[s][t][i] = clamped_load(U, ldu, r, n, col, k);
+                    v[s][t][i] = clamped_load(V, ldv, r, n, col, k);
+                    l[s][t][i] = clamped_load<T>(RG, ldrg, r, n, col, k);
+                    j[s][t][i] = clamped_load<T>(RH, ldrh, r, n, col, k);
+                }
         }
 #pragma unroll
-        for (int c = 0; c < K; ++c) res[c] = (T)fma(1.0, (double)g[c], o[c]);
-        store_row<T, K, VEC>(RG + i * ldrg, k, res);
+        for (int s = 0; s < TPI; ++s) {
+            pin_all(ua[s]);
+            pin_all(va[s]);
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                pin_all(u[s][t]);
+                pin_all(v[s][t]);
+                pin_all(l[s][t]);
+                pin_all(j[s][t]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < TPI; ++s) {
+            const int64_t row0 = (tile0 + s * stride) * 16;
+            mask_mf_chunk<T, K>(row0 + c, n, k, ua[s]);
+            mask_mf_chunk<T, K>(row0 + c, n, k, va[s]);
+            dbl4 acc[CT];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+            mf_products<T, K>(ua[s], -1.0, mg, acc);
+#pragma unroll
+            for (int t = 0; t < CT; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t r = row0 + 4 * i + q;
+                    const int col = 16 * t + c;
+                    T g, hv;
+                    epilogue<T, GRAD>(pw, epsc, p, cs[t], u[s][t][i], v[s][t][i], l[s][t][i], j[s][t][i], g, hv);
+                    if (r < n && col < k) RG[r * ldrg + col] = (T)fma(1.0, (double)g, acc[t][i]);
+                }
+#pragma unroll
+            for (int t = 0; t < CT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+            mf_products<T, K>(ua[s], -1.0, mh, acc);
+            mf_products<T, K>(va[s], -1.0, mg, acc);
+#pragma unroll
+            for (int t = 0; t < CT; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t r = row0 + 4 * i + q;
+                    const int col = 16 * t + c;
+                    T g, hv;
+                    epilogue<T, HVP>(pw, epsc, p, cs[t], u[s][t][i], v[s][t][i], l[s][t][i], j[s][t][i], g, hv);
+                    if (r < n && col < k) RH[r * ldrh + col] = (T)fma(1.0, (double)hv, acc[t][i]);
+                }
+        }
     }
-    double o[K];
-#pragma unroll
-    for (int c = 0; c < K; ++c) o[c] = 0.0;
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const double ur = -1.0 * (double)u[r];
-#pragma unroll
-        for (int c = 0; c < K; ++c) o[c] = fma(ur, mat_at<K, VEC>(MH, k, r, c), o[c]);
-    }
-#pragma unroll
-    for (int r = 0; r < K; ++r) {
-        const double vr = -1.0 * (double)v[r];
-#pragma unroll
-        for (int c = 0; c < K; ++c) o[c] = fma(vr, mat_at<K, VEC>(MG, k, r, c), o[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < K; ++c) res[c] = (T)fma(1.0, (double)hv[c], o[c]);
-    store_row<T, K, VEC>(RH + i * ldrh, k, res);
 }
 
 constexpr int kUnroll = 8;  // gathers in flight per thread in the heavy-chunk kernel
@@ -721,10 +742,10 @@ pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, 
     return PSPEC_OK;
 }
 
-// The fused epilogue fits in registers while a lane holds four rows of at most 128 bytes.
+// The fused kernels run on the matrix cores up to k = 32; wider blocks take the stand-alone path.
 template <typename T, int K>
 constexpr bool rhvp_fused() {
-    return K * (int)sizeof(T) <= 128;
+    return K <= 32;
 }
 
 // Riemannian gradient and Hessian-vector product on Gr(k, n).  Workspace: level-1 partials
@@ -742,28 +763,27 @@ pspec_status launch_rhvp(Graph *g, int k, const T *U, int64_t ldu, const T *V, i
     const T epsc = (T)std::pow(eps, p - 2.0);
     const pspec_status st = edge_pass<T, WT, K, HVP>(g, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, p, eps, F_col, nullptr, s);
     if (st != PSPEC_OK) return st;
-    const unsigned rows = (unsigned)((n + kBlock - 1) / kBlock);
     if constexpr (rhvp_fused<T, K>()) {
-        finalize_gram<T, K, VEC><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc,
-                                                                 p, g->scalars, g->k_max, part);
+        finalize_gram<T, K><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc, p,
+                                                            g->scalars, g->k_max, part);
         sum_partials(part, (int)kk, mid, Mw, MG_out, s, 2 * (int64_t)kk);
         sum_partials(part + kk, (int)kk, mid, Mw + kk, nullptr, s, 2 * (int64_t)kk);
-        apply_rhvp<T, K, VEC><<<rows, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc, p,
-                                                      g->scalars, g->k_max, Mw, Mw + kk);
+        apply_rhvp<T, K, VEC><<<mf_grid(n), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc, p,
+                                                            g->scalars, g->k_max, Mw, Mw + kk);
     } else {  // wide rows: finalize, then the two projections with the stand-alone kernels, in place
         finalize<T, K, HVP><<<grid_for(n, kBlock / K, 65536), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH,
                                                                                ldrh, pw, epsc, p, g->scalars,
                                                                                g->k_max);
-        gram_partial<T, K, VEC, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RG,
-                                                                               ldrg, part);
+        gram_partial<T, K, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RG, ldrg,
+                                                                          part);
         sum_partials(part, (int)kk, mid, Mw, MG_out, s);
-        gram_partial<T, K, VEC, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RH,
-                                                                               ldrh, part);
+        gram_partial<T, K, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RH, ldrh,
+                                                                          part);
         sum_partials(part, (int)kk, mid, Mw + kk, nullptr, s);
-        apply_rows<T, K, VEC, false, false, true><<<rows, kBlock, 0, s>>>(
-            n, k, 1.0, RG, ldrg, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr, 0, nullptr, 0.0, RG, ldrg);
-        apply_rows<T, K, VEC, false, true, true><<<rows, kBlock, 0, s>>>(
-            n, k, 1.0, RH, ldrh, U, ldu, nullptr, 0, 0.0, Mw + kk, -1.0, V, ldv, Mw, -1.0, RH, ldrh);
+        launch_apply<T, K, VEC, false, false, true>(s, n, k, 1.0, RG, ldrg, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr,
+                                                    0, nullptr, 0.0, RG, ldrg);
+        launch_apply<T, K, VEC, false, true, true>(s, n, k, 1.0, RH, ldrh, U, ldu, nullptr, 0, 0.0, Mw + kk, -1.0, V,
+                                                   ldv, Mw, -1.0, RH, ldrh);
     }
     PSPEC_HIP(hipGetLastError());
     return PSPEC_OK;
