@@ -84,17 +84,17 @@ typedef struct ihipEvent_t *pspec_event;
  *   stream          the schedule is built on this stream; the call synchronises it once to read
  *                   back the sizes of the schedule.
  *   out             receives the handle.
- * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed one
- * wavefront-group per row in node order; longer rows are cut into chunks of at most
- * PSPEC_CHUNK edges, each processed by a whole workgroup, and rows spanning several chunks are
+ * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
+ * 16-lane group per row in node order; longer rows are cut into chunks of at most PSPEC_CHUNK
+ * edges, handed out in a fixed order to one wavefront each, and rows spanning several chunks are
  * combined in a fixed order afterwards, so every result is bit-reproducible.  The CSR is
  * validated on the device (rowptr monotone with rowptr[0] = 0 and rowptr[n] = nnz, every column
  * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  The handle allocates its own device
  * memory (schedule, per-tile FP64 partial sums, chunk scratch): about
- * 8 * 4 * k_max * (n / 256 + chunks) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
+ * 8 * 4 * k_max * (n / 256 + 4 * CUs) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
  */
 #define PSPEC_LIGHT_MAX 32
-#define PSPEC_CHUNK 1024
+#define PSPEC_CHUNK 512
 pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
                                 const void *w, pspec_dtype wtype, int k_max, pspec_stream stream,
                                 pspec_graph *out);

@@ -332,71 +332,135 @@ __global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
     }
 }
 
-// Heavy rows: one workgroup per chunk of at most PSPEC_CHUNK edges.  The chunk's neighbour byte
-// offsets and weights are staged in LDS with coalesced loads; the workgroup's 256/K edge slots then
-// stream them with UNR gathers in flight per thread.
+// Heavy rows: chunks of at most PSPEC_CHUNK edges handed out in a fixed order to persistent waves
+// (wave W of the grid takes chunks W, W + NW, W + 2 NW, ...).  A wave stages its chunk's neighbour
+// byte offsets and weights in its own slice of LDS (no workgroup barrier), runs ES = 64 / K edge
+// slots of K column lanes with UNR gathers in flight per lane (slots past the chunk gather the row
+// itself with weight 0, so every load is unconditional), adds the slots up with cross-lane sums,
+// writes the chunk's rows (or its scratch row when the row spans several chunks) and carries the
+// FP64 column sums of w |x|^p and L_i v_i from chunk to chunk.  Each workgroup writes one partial
+// row, its waves added in order, so the result does not depend on timing.
 template <typename T, typename WT, int K, int MODE, int UNR>
-__global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
-    constexpr int EPB = kBlock / K;
-    __shared__ uint32_t s_ou[PSPEC_CHUNK], s_ov[PSPEC_CHUNK];  // neighbour byte offsets into U, V
-    __shared__ T s_w[PSPEC_CHUNK];
-    __shared__ double s_r[3][kBlock];
-    const Chunk ch = a.chunks[blockIdx.x];
-    const int len = (int)(ch.end - ch.beg);
-    const int tid = threadIdx.x;
-    for (int t = tid; t < len; t += kBlock) {
-        const uint32_t j = (uint32_t)a.col[ch.beg + t];
-        s_ou[t] = j * a.ldu_b;
-        s_ov[t] = j * a.ldv_b;
-        s_w[t] = (T)a.w[ch.beg + t];
-    }
-    __syncthreads();
-    const int c = tid % K, e = tid / K;
+__global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t n_chunks) {
+    constexpr int KW = K < 64 ? K : 64;  // column lanes of an edge slot
+    constexpr int ES = 64 / KW;          // edge slots per wave
+    constexpr int NWB = kBlock / 64;     // waves per workgroup
+    __shared__ uint32_t s_ou[NWB][PSPEC_CHUNK], s_ov[NWB][PSPEC_CHUNK];  // neighbour byte offsets into U, V
+    __shared__ T s_w[NWB][PSPEC_CHUNK];
+    __shared__ double s_acc[NWB][2][KW];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = lane % KW, e = lane / KW;
     const int cl = c < a.k ? c : a.k - 1;
     const uint32_t cb = (uint32_t)cl * (uint32_t)sizeof(T);
     const auto rU = make_rsrc(a.U, a.U_bytes);
     const auto rV = make_rsrc(a.V, a.V_bytes);
-    const uint32_t row = (uint32_t)ch.row;
-    const T ui = bload<T>(rU, row * a.ldu_b + cb);
-    T vi = 0;
-    if (MODE == HVP) vi = bload<T>(rV, row * a.ldv_b + cb);
-    T Ls = 0, Js = 0, Ns = 0;
-    for (int base = 0; base < len; base += EPB * UNR) {
-        T uj[UNR], vj[UNR], wv[UNR];
+    double Nacc = 0.0, Sacc = 0.0;
+    const int64_t NW = (int64_t)gridDim.x * NWB;
+    for (int64_t ci = (int64_t)blockIdx.x * NWB + wv; ci < n_chunks; ci += NW) {
+        const Chunk ch = a.chunks[ci];
+        const int len = (int)(ch.end - ch.beg);
+        for (int t0 = 0; t0 < len; t0 += 4 * 64) {  // four ids per lane in flight
+            uint32_t jj[4];
+            WT ww[4];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int idx = base + u * EPB + e;
-            const bool ok = idx < len;
-            wv[u] = ok ? s_w[idx] : (T)0;
-            uj[u] = ok ? bload<T>(rU, s_ou[idx] + cb) : ui;
-            vj[u] = (MODE == HVP && ok) ? bload<T>(rV, s_ov[idx] + cb) : vi;
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + 64 * u + lane;
+                const int64_t src = ch.beg + (t < len ? t : len - 1);
+                jj[u] = (uint32_t)a.col[src];
+                ww[u] = a.w[src];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                pin(jj[u]);
+                pin(ww[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + 64 * u + lane;
+                if (t < len) {
+                    s_ou[wv][t] = jj[u] * a.ldu_b;
+                    s_ov[wv][t] = jj[u] * a.ldv_b;
+                    s_w[wv][t] = (T)ww[u];
+                }
+            }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t row = (uint32_t)ch.row;
+        const uint32_t own_u = row * a.ldu_b + cb, own_v = row * a.ldv_b + cb;
+        const T ui = bload<T>(rU, own_u);
+        const T vi = MODE == HVP ? bload<T>(rV, own_v) : T(0);
+        T Ls = 0, Js = 0, Ns = 0;
+        for (int base = 0; base < len; base += ES * UNR) {
+            // all staged offsets of the batch are read before any is used (see pin)
+            uint32_t ou[UNR], ov[UNR];
+            T uj[UNR], vj[UNR], wt[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wv[u], Ls, Js, Ns);
+            for (int u = 0; u < UNR; ++u) {
+                const int idx = base + u * ES + e;
+                const int ix = idx < len ? idx : 0;
+                ou[u] = s_ou[wv][ix];
+                if (MODE == HVP) ov[u] = s_ov[wv][ix];
+                wt[u] = s_w[wv][ix];
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                pin(ou[u]);
+                if (MODE == HVP) pin(ov[u]);
+                pin(wt[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const bool ok = base + u * ES + e < len;
+                wt[u] = ok ? wt[u] : T(0);
+                uj[u] = bload<T>(rU, ok ? ou[u] + cb : own_u);
+                if (MODE == HVP) vj[u] = bload<T>(rV, ok ? ov[u] + cb : own_v);
+                else vj[u] = T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wt[u], Ls, Js, Ns);
+        }
+        double L = (double)Ls, J = (double)Js, N = (double)Ns;
+#pragma unroll
+        for (int o = KW; o < 64; o <<= 1) {
+            L += __shfl_xor(L, o);
+            if (MODE == HVP) J += __shfl_xor(J, o);
+            N += __shfl_xor(N, o);
+        }
+        if (e == 0 && c < a.k) {
+            if (ch.slot < 0) {
+                if (MODE != OBJ) a.L[(int64_t)row * a.ldl + c] = (T)L;
+                if (MODE == HVP) a.J[(int64_t)row * a.ldj + c] = (T)J;
+            } else {
+                a.scratch[((int64_t)ch.slot * 2 + 0) * a.k_max + c] = L;
+                a.scratch[((int64_t)ch.slot * 2 + 1) * a.k_max + c] = J;
+            }
+            Nacc += N;
+            if (MODE == HVP) Sacc += L * (double)vi;
+        }
+        // the next chunk's staging must not overtake this chunk's LDS reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    s_r[0][tid] = (double)Ls;
-    s_r[1][tid] = (double)Js;
-    s_r[2][tid] = (double)Ns;
+    if (e == 0) {
+        s_acc[wv][0][c] = Nacc;
+        s_acc[wv][1][c] = Sacc;
+    }
     __syncthreads();
-    if (tid < K && tid < a.k) {
-        double L = 0.0, J = 0.0, N = 0.0;
-        for (int q = 0; q < EPB; ++q) {
-            L += s_r[0][q * K + tid];
-            J += s_r[1][q * K + tid];
-            N += s_r[2][q * K + tid];
-        }
-        if (ch.slot < 0) {
-            if (MODE != OBJ) a.L[(int64_t)row * a.ldl + tid] = (T)L;
-            if (MODE == HVP) a.J[(int64_t)row * a.ldj + tid] = (T)J;
-        } else {
-            a.scratch[((int64_t)ch.slot * 2 + 0) * a.k_max + tid] = L;
-            a.scratch[((int64_t)ch.slot * 2 + 1) * a.k_max + tid] = J;
+    const int tid = threadIdx.x;
+    if (tid < a.k) {
+        double N = 0.0, S = 0.0;
+        for (int w = 0; w < NWB; ++w) {
+            N += s_acc[w][0][tid];
+            S += s_acc[w][1][tid];
         }
         double *prow = a.partials + (a.part_base + blockIdx.x) * kQ * a.k;
         prow[0 * a.k + tid] = N;
         prow[1 * a.k + tid] = 0.0;
         prow[2 * a.k + tid] = 0.0;
-        prow[3 * a.k + tid] = (MODE == HVP) ? L * (double)vi : 0.0;
+        prow[3 * a.k + tid] = S;
     }
 }
 
@@ -676,7 +740,14 @@ __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *
     }
 }
 
-constexpr int kUnroll = 8;  // gathers in flight per thread in the heavy-chunk kernel
+// Gathers in flight per lane in the heavy-chunk kernel: 32 edges per wave (64 / K edge slots), at
+// most 16 per lane (8 in FP64, so that four workgroups per CU stay resident).
+template <typename T, int K>
+constexpr int heavy_unroll() {
+    constexpr int slots = K < 64 ? 64 / K : 1;
+    constexpr int cap = sizeof(T) == 8 ? 8 : 16;
+    return 32 / slots > cap ? cap : (32 / slots < 2 ? 2 : 32 / slots);
+}
 
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
     int64_t g = (items + per_block - 1) / per_block;
@@ -715,13 +786,14 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.part_base = g->tiles;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
     edge_light<T, WT, K, MODE><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
-    if (g->n_chunks > 0) edge_heavy<T, WT, K, MODE, kUnroll><<<(unsigned)g->n_chunks, kBlock, 0, s>>>(a);
+    const int64_t hb = g->heavy_grid;
+    if (hb > 0) edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>()><<<(unsigned)hb, kBlock, 0, s>>>(a, g->n_chunks);
     if (g->n_split > 0 && MODE != OBJ)
         combine_split<T, MODE><<<grid_for(g->n_split * k, kBlock, 1 << 30), kBlock, 0, s>>>(
             g->splits, g->n_split, g->chunk_scratch, k, g->k_max, L, ldl, J, ldj);
     if (g->ev_after) PSPEC_HIP(hipEventRecord(g->ev_after, s));
     const int W = kQ * k;
-    reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + g->n_chunks, W, g->red1);
+    reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + hb, W, g->red1);
     reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F);
     return PSPEC_OK;
 }

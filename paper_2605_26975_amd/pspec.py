@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("PSPEC_LIBRARY") or os.path.join(os.path.dirname(os.pa
 PSPEC_F32, PSPEC_F64 = 0, 1
 _STATUS = {0: "PSPEC_OK", 1: "PSPEC_ERR_ARG", 2: "PSPEC_ERR_UNSUPPORTED", 3: "PSPEC_ERR_HIP", 4: "PSPEC_ERR_WORKSPACE"}
 LIGHT_MAX = 32
-CHUNK = 1024
+CHUNK = 512
 K_MAX = 64
 
 _lib = None
