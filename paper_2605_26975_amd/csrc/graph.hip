@@ -2,8 +2,8 @@
 //
 // Rows with at most PSPEC_LIGHT_MAX neighbours are processed in node order by the light edge
 // kernel (a group of lanes per row, kTileRows rows per workgroup).  Longer rows are cut into
-// chunks of at most PSPEC_CHUNK edges, one workgroup per chunk; rows with several chunks are
-// summed afterwards in chunk order.  The schedule is built with three integer kernels
+// chunks of at most PSPEC_CHUNK edges, handed in a fixed order to the waves of the persistent
+// heavy-chunk kernel; rows with several chunks are summed afterwards in chunk order.  The schedule is built with three integer kernels
 // (per-block counts, one-block exclusive scan, per-block emission with a block-local scan), so
 // chunk order, and with it every floating-point sum, is the same on every run.
 #include <cstdarg>
