@@ -78,3 +78,19 @@ def test_dense_argument_errors(libpspec):
     assert libpspec.pspec_retract(100, 4, 0, 256, 3, 512, 4, 0.1, 768, 4, None, 1024, 1 << 30, None) == 1
     assert libpspec.pspec_retract(100, 65, 0, 256, 65, 512, 65, 0.1, 768, 65, None, 1024, 1 << 30, None) == 2
     assert libpspec.pspec_retract(100, 4, 0, 256, 4, 512, 4, 0.1, 768, 4, None, 1024, 16, None) == 4
+
+
+def test_rhvp_host_side_errors(libpspec):
+    """pspec_rhvp rejects a NULL graph before any launch, and the dense workspace covers the two
+    k x k partials per Gram workgroup it needs."""
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    libpspec.pspec_rhvp.argtypes = [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp,
+                                    ctypes.c_size_t, vp]
+    libpspec.pspec_rhvp.restype = ctypes.c_int
+    libpspec.pspec_last_error.restype = ctypes.c_char_p
+    assert libpspec.pspec_rhvp(None, 0, 16, 256, 32, 320, 32, 1.5, 1e-8, 512, 16, 768, 16, None, None, 1024,
+                               1 << 30, None) == 1
+    assert b"rhvp: NULL graph" in libpspec.pspec_last_error()
+    libpspec.pspec_dense_workspace_bytes.argtypes = [i32]
+    libpspec.pspec_dense_workspace_bytes.restype = ctypes.c_size_t
+    assert libpspec.pspec_dense_workspace_bytes(16) >= 2 * 1024 * 16 * 16 * 8
