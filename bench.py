@@ -220,6 +220,8 @@ def main() -> int:
                          "and two pspec_project calls (identical results)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements (per-call times, cold edge pass, streaming-read rate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     ap.add_argument("--summarize-profile", nargs=6, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_TRACE",
@@ -315,6 +317,67 @@ def main() -> int:
         ok = bool(torch.isfinite(F).item()) and bool(torch.isfinite(RH).all().item())
         return total_ms / steps, edge_ms, ok
 
+    def extras(reps: int = 10):
+        """FP32 side measurements (not the metric): each call of the step on its own, the unfused
+        pspec_hvp call (edge pass + epilogue), the edge pass with the Infinity Cache flushed before
+        every run, and a streaming-read reference rate of this GPU (pspec_dot over 2 GiB)."""
+        dtype = torch.float32
+        U, V, keep = make_inputs(dtype)
+        RG, RH, Un, HV, G = (torch.empty((n, k), dtype=dtype, device=dev) for _ in range(5))
+        MG = torch.empty((k, k), dtype=torch.float64, device=dev)
+        Fc = torch.empty(k, dtype=torch.float64, device=dev)
+        F = torch.empty((), dtype=torch.float64, device=dev)
+        calls = {
+            "rhvp": lambda: pspec.rhvp(dg, U, V, p, eps, RH=RH, RG=RG, MG=MG, F_col=Fc),
+            "hvp": lambda: pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc),
+            "project": lambda: pspec.project(U, G, out=RG, M=MG),
+            "retract": lambda: pspec.retract(U, RG, -1e-3, out=Un),
+            "objective": lambda: pspec.objective(dg, Un, p, F_col=Fc, F=F),
+        }
+        ms = {}
+        for name, fn in calls.items():
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms[name] = a.elapsed_time(b) / reps
+        # edge pass with a cold Infinity Cache: 512 MiB written before every run
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        evs = HipEvents(reps)
+        for i in range(reps):
+            flush.zero_()
+            dg.set_timing_events_raw(*evs.pairs[i])
+            calls["hvp"]()
+            dg.set_timing_events_raw(None, None)
+        torch.cuda.synchronize()
+        cold = [evs.elapsed_ms(i) for i in range(reps)]
+        evs.close()
+        del flush
+        # streaming read: sum_ij A_ij B_ij over two 1 GiB blocks
+        rows = (1 << 30) // (16 * 4)
+        A = torch.ones((rows, 16), dtype=dtype, device=dev)
+        B = torch.ones((rows, 16), dtype=dtype, device=dev)
+        pspec.dot(A, B)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            pspec.dot(A, B)
+        b.record()
+        torch.cuda.synchronize()
+        read_gbs = 2 * (1 << 30) / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+        del A, B
+        return {
+            "call_ms": ms,
+            "hvp_call_value": nnz * k / (ms["hvp"] * 1e-3),
+            "edge_pass_cold_ms": float(np.mean(cold)),
+            "read_stream_GBps": read_gbs,
+        }
+
     if args.copy_calibration:
         # Y <- 1 * X + 0 * Y through the library's axpby: reads X once, writes Y once (a plain copy)
         src = torch.ones((COPY_BYTES // 64, 16), dtype=torch.float32, device=dev)
@@ -325,6 +388,7 @@ def main() -> int:
         del src, dst
     t32, edge32, ok32 = run(torch.float32, args.steps, args.warmup)
     print(f"[bench] fp32 step {t32:.3f} ms, edge pass {np.mean(edge32):.3f} ms", file=sys.stderr, flush=True)
+    more = None if args.no_extras else extras()
     fp64 = None
     if not args.no_fp64:
         t64, edge64, ok64 = run(torch.float64, max(3, args.steps // 4), 1)
@@ -378,6 +442,8 @@ def main() -> int:
             "launch_ms": edge_ms,
         },
         "edge_pass_value": nnz * k / (edge_ms * 1e-3),
+        "measurements": None if more is None else dict(
+            more, edge_frac_of_read_stream=achieved / more["read_stream_GBps"]),
         "fp64": fp64,
         "speedup_fp32_over_fp64": (fp64["ms_per_step"] / t32) if fp64 else None,
         "finite": ok32,

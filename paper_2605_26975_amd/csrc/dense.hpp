@@ -441,6 +441,7 @@ __global__ __launch_bounds__(kBlock) void apply_rows_wide(int64_t n, int k, doub
                                                    const T *__restrict__ X, int64_t ldx,
                                                    const double *__restrict__ M2, double s2, T *__restrict__ out,
                                                    int64_t ldo) {
+    constexpr int RU = VEC ? K : 1;  // products fully unrolled only with compile-time operand offsets
     __shared__ double sM1[VEC ? 1 : K * K], sM2[VEC || !HAS_X ? 1 : K * K];
     if constexpr (!VEC) {
         stage_matrix<K>(M1, k, sM1);
@@ -460,14 +461,14 @@ __global__ __launch_bounds__(kBlock) void apply_rows_wide(int64_t n, int k, doub
     double o[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) o[c] = 0.0;
-#pragma unroll(VEC ? K : 1)
+#pragma unroll RU
     for (int r = 0; r < K; ++r) {
         const double av = s1 * (AXPY ? (double)(T)((double)a[r] + t * (double)a2[r]) : (double)a[r]);
 #pragma unroll
         for (int c = 0; c < K; ++c) o[c] = fma(av, M1[r * K + c], o[c]);
     }
     if constexpr (HAS_X) {
-#pragma unroll(VEC ? K : 1)
+#pragma unroll RU
         for (int r = 0; r < K; ++r) {
             const double xv = s2 * (double)x[r];
 #pragma unroll
