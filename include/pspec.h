@@ -91,7 +91,7 @@ typedef struct ihipEvent_t *pspec_event;
  * validated on the device (rowptr monotone with rowptr[0] = 0 and rowptr[n] = nnz, every column
  * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  The handle allocates its own device
  * memory (schedule, per-tile FP64 partial sums, chunk scratch): about
- * 8 * 4 * k_max * (n / 256 + 4 * CUs) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
+ * 8 * 4 * k_max * (n / 256 + 8 * CUs) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
  */
 #define PSPEC_LIGHT_MAX 32
 #define PSPEC_CHUNK 512

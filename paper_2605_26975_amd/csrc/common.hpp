@@ -51,16 +51,7 @@ struct Split {
 };
 
 constexpr int kBlock = 256;        // threads per workgroup of every kernel here
-constexpr int kHeavyPerCU = 4;     // resident workgroups per CU of the persistent heavy-chunk kernel
-
-// Workgroups of the heavy-chunk kernel (four waves each, one chunk per wave at a time): no more than
-// stay resident together, so that no second round of workgroups starts after the first.  Fixed
-// per graph (every mode uses the same partition of the chunks); each writes one FP64 partial row
-// after the tiles' rows.
-inline int64_t heavy_blocks(int64_t n_chunks, int cus) {
-    const int64_t b = (n_chunks + 3) / 4, cap = (int64_t)kHeavyPerCU * (cus > 0 ? cus : 1);
-    return b < cap ? b : cap;
-}
+constexpr int kHeavyPerCUMax = 8;  // most resident workgroups per CU of the persistent heavy-chunk kernel
 constexpr int kTileRows = 256;     // rows per light-kernel workgroup (one FP64 partial row each)
 constexpr int kQ = 4;              // FP64 partial sums per column: N, D, a = phi^T v, S_L = L^T v
 constexpr int kReduceSlices = 256; // first-stage workgroups of the deterministic reduction
@@ -79,10 +70,11 @@ struct Graph {
     int device = 0;
     int64_t tiles = 0;         // light tiles = ceil(n / kTileRows)
     int64_t heavy_rows = 0, n_chunks = 0, n_split = 0;
-    int64_t heavy_grid = 0;    // workgroups of the heavy-chunk kernel (heavy_blocks)
+    int64_t heavy_grid_max = 0;  // most workgroups of the heavy-chunk kernel (one partial row each)
+    int cus = 1;                 // compute units of the device
     Chunk *chunks = nullptr;   // device [n_chunks]
     Split *splits = nullptr;   // device [n_split]
-    double *partials = nullptr;   // device [(tiles + heavy_grid) * kQ * k_max]
+    double *partials = nullptr;   // device [(tiles + heavy_grid_max) * kQ * k_max]
     double *red1 = nullptr;       // device [kReduceSlices * kQ * k_max]
     double *scalars = nullptr;    // device [kScalars * k_max]
     double *chunk_scratch = nullptr;  // device [n_chunks * 2 * k_max] (row partials of split rows)

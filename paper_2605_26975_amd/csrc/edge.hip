@@ -150,8 +150,14 @@ constexpr int light_cpl() {
     return K > 16 ? K / 16 : 1;
 }
 
+// Waves per SIMD the light kernel is compiled for (k = 32 in FP32 sits just above 128 VGPRs).
+template <typename T, int K>
+constexpr int light_waves() {
+    return (sizeof(T) == 4 && K == 32) ? 4 : 1;
+}
+
 template <typename T, typename WT, int K, int MODE>
-__global__ __launch_bounds__(kBlock) void edge_light(EdgeArgs<T, WT> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_waves<T, K>()))) void edge_light(EdgeArgs<T, WT> a) {
     constexpr int G = 16;
     constexpr int CPL = light_cpl<K>();  // columns per lane
     constexpr int KL = K / CPL;          // column lanes per edge slot
@@ -741,12 +747,30 @@ __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *
 }
 
 // Gathers in flight per lane in the heavy-chunk kernel: 32 edges per wave (64 / K edge slots), at
-// most 16 per lane (8 in FP64, so that four workgroups per CU stay resident).
+// most 8 per lane (more registers per wave cost more in resident waves than they gain).
 template <typename T, int K>
 constexpr int heavy_unroll() {
     constexpr int slots = K < 64 ? 64 / K : 1;
-    constexpr int cap = sizeof(T) == 8 ? 8 : 16;
-    return 32 / slots > cap ? cap : (32 / slots < 2 ? 2 : 32 / slots);
+    return 32 / slots > 8 ? 8 : (32 / slots < 2 ? 2 : 32 / slots);
+}
+
+// Workgroups of the persistent heavy-chunk kernel for this element type and k: as many as stay
+// resident together (from the occupancy of the HVP variant, the hungriest, so every mode shares
+// the partition of the chunks and the per-column sums agree bit for bit across entry points), at
+// most kHeavyPerCUMax per CU and one per four chunks.
+template <typename T, typename WT, int K>
+int64_t heavy_grid(const Graph *g) {
+    static int per_cu = 0;  // per instantiation; every thread computes the same value
+    if (per_cu == 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, edge_heavy<T, WT, K, HVP, heavy_unroll<T, K>()>,
+                                                         kBlock, 0) != hipSuccess ||
+            v < 1)
+            v = 1;
+        per_cu = v < kHeavyPerCUMax ? v : kHeavyPerCUMax;
+    }
+    const int64_t want = (g->n_chunks + 3) / 4, cap = (int64_t)per_cu * g->cus;
+    return want < cap ? want : cap;
 }
 
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
@@ -786,7 +810,7 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.part_base = g->tiles;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
     edge_light<T, WT, K, MODE><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
-    const int64_t hb = g->heavy_grid;
+    const int64_t hb = heavy_grid<T, WT, K>(g);
     if (hb > 0) edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>()><<<(unsigned)hb, kBlock, 0, s>>>(a, g->n_chunks);
     if (g->n_split > 0 && MODE != OBJ)
         combine_split<T, MODE><<<grid_for(g->n_split * k, kBlock, 1 << 30), kBlock, 0, s>>>(

@@ -250,8 +250,10 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->n_split = host_tot[2];
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
-    g->heavy_grid = heavy_blocks(g->n_chunks, cus);
-    const int64_t P = g->tiles + g->heavy_grid;
+    g->cus = cus > 0 ? cus : 1;
+    const int64_t hmax = (int64_t)kHeavyPerCUMax * g->cus, hwant = (g->n_chunks + 3) / 4;
+    g->heavy_grid_max = hwant < hmax ? hwant : hmax;
+    const int64_t P = g->tiles + g->heavy_grid_max;
     const size_t b_chunks = align256(sizeof(Chunk) * (size_t)g->n_chunks);
     const size_t b_splits = align256(sizeof(Split) * (size_t)g->n_split);
     const size_t b_part = align256(sizeof(double) * (size_t)P * kQ * k_max);
