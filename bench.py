@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -46,11 +47,15 @@ WORKLOADS = {
 
 
 def edge_source_hash() -> str:
-    """Hash of the sources that define the fused edge kernel (traffic figures go stale with them)."""
+    """Hash of the code (comments and whitespace removed) of the sources that define the fused edge
+    kernel: the stored traffic figures go stale when that code changes."""
     h = hashlib.sha256()
     for f in ("edge.hip", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_2605_26975_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2605_26975_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -10,8 +10,8 @@
 // |x|^p = phi x and psi = min(|x|^(p-2), eps^(p-2)).
 //
 // Edge values are accumulated per row in the working precision T; every sum over rows is FP64:
-// each light workgroup (kTileRows rows) and each heavy chunk writes one FP64 partial row
-// [kQ][k], and a two-stage reduction sums them in a fixed order.  The epilogue (finalize) turns
+// each light workgroup (kTileRows rows) and each workgroup of the persistent heavy-chunk kernel
+// writes one FP64 partial row [kQ][k], and a two-stage reduction sums them in a fixed order.  The epilogue (finalize) turns
 // the raw rows L, J (stored in the G and HV outputs) into
 //   G_i  = (p/D) (L_i - F phi_p(u_i))
 //   HV_i = (p/D) ((p-1) J_i - F (p-1) psi(u_i) v_i - G_i a - phi_p(u_i) b),  b = (p/D)(S - F a) = g^T v.
@@ -61,7 +61,7 @@ struct EdgeArgs {
     PowM2<T> pw;
     T epsc;          // eps^(p-2)
     int light_max;
-    double *partials;  // [(tiles + chunks)][kQ][k]
+    double *partials;  // [(tiles + heavy workgroups)][kQ][k]
     const Chunk *chunks;
     double *scratch;   // [chunks][2][k_max]
     int k_max;
