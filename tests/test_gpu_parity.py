@@ -323,3 +323,26 @@ def test_dense_strided_layouts_are_bit_identical(dtype):
         got = run(laid_out(width))
         for a, b in zip(ref, got):
             assert torch.equal(a, b), width
+
+
+@pytest.mark.parametrize("k", [16, 32])
+def test_modes_agree_bitwise_with_heavy_rows(k):
+    """With light, heavy single-chunk and split rows, every entry point partitions the rows and
+    chunks the same way, so the per-column objective agrees bit for bit across objective, grad,
+    hvp and rhvp, and grad's G equals hvp's G."""
+    print(f"[case] modes agree rmat14 k={k}", flush=True)
+    g = gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9)
+    dg = gu.device_graph(g, k)
+    info = dg.info()
+    assert info["heavy_rows"] > 0 and info["split_rows"] > 0
+    U, V = gu.inputs(g.n, k)
+    Ut, Vt = torch.as_tensor(U).cuda(), torch.as_tensor(V).cuda()
+    p, eps = 1.05, 1e-8
+    HV, G, Fc = pspec.hvp(dg, Ut, Vt, p, eps)
+    G2, Fc2 = pspec.grad(dg, Ut, p)
+    F3, Fc3 = pspec.objective(dg, Ut, p)
+    RH, RG, MG, Fc4 = pspec.rhvp(dg, Ut, Vt, p, eps)
+    torch.cuda.synchronize()
+    assert torch.equal(G, G2)
+    for other in (Fc2, Fc3, Fc4):
+        assert torch.equal(Fc, other)
