@@ -225,6 +225,8 @@ def main() -> int:
                          "and two pspec_project calls (identical results)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--permute", action="store_true",
+                    help="relabel the nodes by a seeded random permutation first (node-order sensitivity line)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the side measurements (per-call times, cold edge pass, streaming-read rate)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -254,6 +256,8 @@ def main() -> int:
     k, p, eps = cfg["k"], cfg["p"][-1], cfg["eps"]
     t0 = time.perf_counter()
     g = cfg["graph"]()
+    if args.permute:
+        g = gen.permute(g, seed=7)
     print(f"[bench] graph n={g.n} nnz={g.nnz} generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
           flush=True)
     U_h = gen.block(g.n, k, gen.SEED_U)
@@ -409,7 +413,7 @@ def main() -> int:
     edge_ms = float(np.mean(edge32))
     alg_bytes = algorithmic_edge_bytes(n, nnz, k)
     achieved = alg_bytes / (edge_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, args.layout)
+    traffic = None if args.permute else stored_traffic(args.workload, args.layout)
     out = {
         "metric": METRIC,
         "value": nnz * k / (t32 * 1e-3),
@@ -431,6 +435,7 @@ def main() -> int:
             "p": p,
             "eps": eps,
             "layout": args.layout,
+            "node_order": "random permutation (seed 7)" if args.permute else "generator order",
             "step": ("rhvp (grad, HVP, both Grassmann projections)" if args.step == "fused" else
                      "hvp (fused grad) + 2x project") + " + retract + objective",
             "edge_col_updates_per_step": nnz * k,

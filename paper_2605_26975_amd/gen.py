@@ -84,6 +84,23 @@ def edge_uniform(seed: int, lo_id: np.ndarray, hi_id: np.ndarray, lo: float, hi:
     return (lo + (hi - lo) * u).astype(np.float32)
 
 
+def permute(g: Graph, seed: int) -> Graph:
+    """The same graph with node ids relabelled by a seeded random permutation (new id = perm[old]),
+    weights carried with their edges; columns ascend within each row of the result."""
+    perm = np.random.default_rng(seed).permutation(g.n).astype(np.int64)
+    deg = np.diff(g.rowptr)
+    rows = np.repeat(perm, deg)
+    cols = perm[g.col.astype(np.int64)]
+    key = rows * g.n + cols
+    order = np.argsort(key, kind="stable")
+    new_rows = rows[order]
+    rowptr = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(new_rows, minlength=g.n), out=rowptr[1:])
+    meta = dict(g.meta)
+    meta["permutation_seed"] = seed
+    return Graph(g.n, rowptr, cols[order].astype(np.int32), g.w[order], name=g.name + "-permuted", meta=meta)
+
+
 def csr_from_edges(n: int, i: np.ndarray, j: np.ndarray, weight_fn, name: str = "", meta=None) -> Graph:
     """Build symmetric CSR from an undirected edge list (any order, duplicates and loops allowed).
 

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
+from paper_2605_26975_amd import gen
 from tests import pins
 
 
@@ -47,3 +48,27 @@ def test_golden_worked_examples(oracle_lib):
         assert abs(got - F) <= 1e-15 * max(1.0, abs(F)), (name, got, F)
         cases += 1
     assert cases >= 4
+
+
+def test_permuted_graph_is_the_same_graph(oracle_lib):
+    """gen.permute relabels nodes only: degrees and weights move with the nodes, the CSR stays
+    symmetric with ascending columns, and the oracle's outputs are the permuted originals."""
+    g = gen.sbm_bernoulli(600, 3, 0.05, 0.004)
+    h = gen.permute(g, seed=3)
+    perm = np.random.default_rng(3).permutation(g.n)
+    assert h.nnz == g.nnz
+    assert np.array_equal(np.diff(h.rowptr)[perm], np.diff(g.rowptr))
+    Wg, Wh = g.to_dense(), h.to_dense()
+    assert np.array_equal(Wh[np.ix_(perm, perm)], Wg)
+    for i in range(h.n):
+        c = h.col[h.rowptr[i]:h.rowptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+    U = gen.block(g.n, 4, gen.SEED_U).astype(np.float64)
+    V = gen.block(g.n, 4, gen.SEED_V).astype(np.float64)
+    Up, Vp = np.empty_like(U), np.empty_like(V)
+    Up[perm], Vp[perm] = U, V
+    HV, G, Fc = oracle_lib.hvp(g.rowptr, g.col, g.w.astype(np.float64), U, V, 1.3, 1e-8)
+    HVp, Gp, Fcp = oracle_lib.hvp(h.rowptr, h.col, h.w.astype(np.float64), Up, Vp, 1.3, 1e-8)
+    assert np.allclose(Fcp, Fc, rtol=1e-13)
+    assert np.allclose(Gp[perm], G, rtol=1e-12, atol=1e-15)
+    assert np.allclose(HVp[perm], HV, rtol=1e-12, atol=1e-15)
