@@ -9,7 +9,9 @@ below are this implementation's (see the readings in the design notes):
 * geometry: P_U(Z) = Z - U U^T Z, Riemannian gradient P_U(G), Riemannian Hessian
   P_U(H eta) - eta (U^T G), retraction qf(U + t eta) (all on the GPU through the C ABI);
 * Newton: Steihaug-Toint truncated CG (stop on negative curvature, or when
-  ||r|| <= ||g|| min(||g||^theta, kappa)), then Armijo backtracking on F(R_U(t eta));
+  ||r|| <= ||g|| min(||g||^theta, kappa)) inside a trust region whose radius follows the ratio of
+  actual to model decrease (`rtr`, the default), or followed by Armijo backtracking on
+  F(R_U(t eta)) (`Solver.newton`);
 * p-continuation: p = 2.0, 1.8, ... down to the target, each level warm-started;
 * k-means: Lloyd iterations from k-means++ seeds (fixed seed, several restarts) on the rows of U.
 
@@ -136,6 +138,94 @@ class Solver:
         return U, info
 
 
+@dataclass
+class TrustRegionOptions:
+    max_outer: int = 60
+    rel_tol: float = 1e-5       # stop when ||grad|| <= rel_tol * ||grad at the first iterate||
+    abs_tol: float = 0.0
+    tcg_max: int = 60
+    kappa: float = 0.1
+    theta: float = 1.0
+    rho_accept: float = 0.1     # accept the step when the actual/model decrease ratio exceeds this
+    delta_bar: float | None = None  # largest radius (default sqrt(k))
+    delta0: float | None = None     # first radius (default delta_bar / 8)
+
+
+def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | None = None):
+    """Riemannian trust-region Newton on Gr(k, n) (Absil, Baker and Gallivan's RTR, the method behind
+    the paper's Newton / truncated-CG solver): the Newton system is solved by Steihaug-Toint
+    truncated CG inside a ball of radius Delta, the step is accepted by the ratio rho of actual to
+    model decrease, and Delta shrinks or grows with rho.  Returns the final U and a log."""
+    opt = opt or TrustRegionOptions()
+    s = solver
+    k = s.k
+    delta_bar = opt.delta_bar if opt.delta_bar is not None else float(k) ** 0.5
+    delta = opt.delta0 if opt.delta0 is not None else delta_bar / 8.0
+    info = NewtonInfo(p=p)
+    U = pspec.axpby(1.0, U, 0.0, torch.empty_like(U))  # working copy
+    Heta = torch.empty_like(U)
+    g0 = None
+    for it in range(opt.max_outer):
+        pspec.grad(s.graph, U, p, G=s.G)
+        pspec.project(U, s.G, out=s.rgrad, M=s.MG)
+        gg = s.dot(s.rgrad, s.rgrad)
+        gn = gg ** 0.5
+        Fu = s.F(U, p)
+        info.F.append(Fu)
+        info.grad_norm.append(gn)
+        if g0 is None:
+            g0 = gn
+        if gn <= max(opt.abs_tol, opt.rel_tol * g0) or not np.isfinite(gn):
+            break
+        # Steihaug-Toint truncated CG for Hess[eta] = -grad within ||eta|| <= delta
+        pspec.axpby(0.0, s.rgrad, 0.0, s.eta)
+        pspec.axpby(0.0, s.rgrad, 0.0, Heta)
+        pspec.axpby(1.0, s.rgrad, 0.0, s.r)
+        pspec.axpby(-1.0, s.r, 0.0, s.delta)
+        rr, r0 = gg, gn
+        e_e, e_d, d_d = 0.0, 0.0, gg  # <eta,eta>, <eta,delta>, <delta,delta> by recurrence
+        nt = 0
+        for j in range(opt.tcg_max):
+            nt = j + 1
+            s.hess(U, p, s.delta, s.Hd)
+            dHd = s.dot(s.delta, s.Hd)
+            alpha = rr / dHd if dHd > 0.0 else 0.0
+            e_e_new = e_e + 2.0 * alpha * e_d + alpha * alpha * d_d
+            if dHd <= 0.0 or e_e_new >= delta * delta:
+                # to the boundary along delta: ||eta + tau delta|| = delta, tau >= 0
+                tau = (-e_d + ((e_d * e_d + d_d * (delta * delta - e_e)) ** 0.5)) / d_d
+                pspec.axpby(tau, s.delta, 1.0, s.eta)
+                pspec.axpby(tau, s.Hd, 1.0, Heta)
+                break
+            e_e = e_e_new
+            pspec.axpby(alpha, s.delta, 1.0, s.eta)
+            pspec.axpby(alpha, s.Hd, 1.0, Heta)
+            pspec.axpby(alpha, s.Hd, 1.0, s.r)
+            rr_new = s.dot(s.r, s.r)
+            if rr_new ** 0.5 <= r0 * min(r0 ** opt.theta, opt.kappa):
+                break
+            beta = rr_new / rr
+            rr = rr_new
+            e_d = beta * (e_d + alpha * d_d)
+            d_d = rr + beta * beta * d_d
+            pspec.axpby(-1.0, s.r, beta, s.delta)
+        info.tcg_iterations.append(nt)
+        # model decrease m(0) - m(eta) = -<grad, eta> - 1/2 <eta, Hess eta>
+        model = -s.dot(s.rgrad, s.eta) - 0.5 * s.dot(s.eta, Heta)
+        eta_norm = s.dot(s.eta, s.eta) ** 0.5
+        pspec.retract(U, s.eta, 1.0, out=s.Ut)
+        Ft = s.F(s.Ut, p)
+        rho = (Fu - Ft) / model if model > 0.0 else -1.0
+        if rho < 0.25:
+            delta *= 0.25
+        elif rho > 0.75 and eta_norm >= 0.99 * delta:
+            delta = min(2.0 * delta, delta_bar)
+        if rho > opt.rho_accept:
+            pspec.axpby(1.0, s.Ut, 0.0, U)
+        info.iterations = it + 1
+    return U, info
+
+
 def orthonormal_start(n: int, k: int, seed: int, dtype=torch.float32, device="cuda") -> torch.Tensor:
     """qf(X) of a seeded N(0, 1) block (retraction with t = 0)."""
     from . import gen
@@ -211,16 +301,101 @@ def matched_accuracy(a: np.ndarray, b: np.ndarray) -> float:
 
 
 def cluster(graph: pspec.Graph, host_graph, k: int, p: float, dtype=torch.float32, eps: float = 1e-8,
-            seed: int = 0, opt: NewtonOptions | None = None, step: float = 0.2):
-    """p-spectral clustering: continuation from p = 2 to p, Newton-tCG at each level, then k-means.
+            seed: int = 0, opt=None, step: float = 0.2, method: str = "rtr"):
+    """p-spectral clustering: continuation from p = 2 to p, a Riemannian Newton solve at each level
+    (method "rtr": trust region, TrustRegionOptions; "newton": Armijo line search, NewtonOptions),
+    then k-means on the rows of U.
 
     Returns (labels, U, infos, rcut_value); host_graph supplies the CSR used by RCut.
     """
+    if method not in ("rtr", "newton"):
+        raise ValueError(f"unknown method {method!r}")
     solver = Solver(graph, k, dtype, eps)
     U = orthonormal_start(graph.n, k, seed, dtype, graph.device)
     infos = []
     for pl in p_levels(p, step):
-        U, info = solver.newton(U, pl, opt)
+        if method == "rtr":
+            U, info = rtr(solver, U, pl, opt)
+        else:
+            U, info = solver.newton(U, pl, opt)
         infos.append(info)
     labels = kmeans(U.double().cpu().numpy(), k, seed=seed)
     return labels, U, infos, rcut(host_graph.rowptr, host_graph.col, host_graph.w, labels)
+
+
+def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=torch.float64,
+                   seed: int = 0, opt: TrustRegionOptions | None = None, save: str | None = None,
+                   log=print, spec_opt: TrustRegionOptions | None = None) -> dict:
+    """The whole pipeline on a Delaunay graph of 2^r uniform random points (the stand-in for the
+    paper's triangulation matrices, Section 3): trust-region Newton at each p level of the
+    continuation, k-means on the rows of U and RCut after every level.  The p = 2 level is the
+    spectral (Spec) solution the smaller-p levels are compared with; ``spec_opt`` (default ``opt``)
+    sets its limits, since the p = 2 Newton system of a planar graph grows ill-conditioned with n
+    and needs more CG steps than the levels after it.  With ``save`` set, U is
+    written to ``save/U_r{r}_p{p}.npy`` after each level.  Returns a dict with one entry per level."""
+    import os
+    import time
+
+    from . import gen
+
+    t0 = time.perf_counter()
+    g = gen.delaunay(1 << r, seed=seed)
+    t_graph = time.perf_counter() - t0
+    dg = pspec.Graph.from_host(g, "cuda", k_max=k)
+    solver = Solver(dg, k, dtype, 1e-8)
+    U = orthonormal_start(g.n, k, seed, dtype, "cuda")
+    out = {"r": r, "n": g.n, "edges": g.nnz // 2, "k": k, "dtype": str(dtype).replace("torch.", ""),
+           "graph_seconds": round(t_graph, 2), "levels": []}
+    for pl in p_levels(p, step):
+        t1 = time.perf_counter()
+        U, info = rtr(solver, U, pl, spec_opt if (pl == 2.0 and spec_opt is not None) else opt)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t1
+        Uh = U.double().cpu().numpy()
+        labels = kmeans(Uh, k, seed=seed, n_init=3)
+        lev = {"p": pl, "outer": info.iterations, "tcg": int(sum(info.tcg_iterations)), "F": info.F[-1],
+               "grad_rel": info.grad_norm[-1] / info.grad_norm[0], "rcut": rcut(g.rowptr, g.col, g.w, labels),
+               "solve_seconds": round(t_solve, 2)}
+        out["levels"].append(lev)
+        log(f"r={r} p={pl:.2f} outer {lev['outer']:3d} tcg {lev['tcg']:5d} F {lev['F']:.6e} "
+            f"|g|/|g0| {lev['grad_rel']:.1e} RCut {lev['rcut']:.5f} {t_solve:.1f}s")
+        if save:
+            os.makedirs(save, exist_ok=True)
+            np.save(os.path.join(save, f"U_r{r}_p{pl:.2f}.npy"), Uh)
+    spec, last = out["levels"][0]["rcut"], out["levels"][-1]["rcut"]
+    out["rcut_spec"], out["rcut_pspec"] = spec, last
+    out["rcut_gain_percent"] = 100.0 * (spec - last) / spec
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="p-spectral clustering of Delaunay graphs of 2^r random points "
+                                             "in the unit square: RCut at p = 2 against the smallest p")
+    ap.add_argument("--r", type=int, nargs="+", default=[16])
+    ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--p", type=float, default=1.2)
+    ap.add_argument("--step", type=float, default=0.2)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f64")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-outer", type=int, default=60)
+    ap.add_argument("--tcg-max", type=int, default=60)
+    ap.add_argument("--rel-tol", type=float, default=None)
+    ap.add_argument("--spec-max-outer", type=int, default=100, help="outer limit at p = 2")
+    ap.add_argument("--spec-tcg-max", type=int, default=300, help="tCG limit at p = 2")
+    ap.add_argument("--save", default=None, help="directory for U after each p level (.npy)")
+    a = ap.parse_args(argv)
+    dtype = torch.float64 if a.dtype == "f64" else torch.float32
+    rel = a.rel_tol if a.rel_tol is not None else (1e-6 if dtype == torch.float64 else 1e-4)
+    opt = TrustRegionOptions(max_outer=a.max_outer, tcg_max=a.tcg_max, rel_tol=rel)
+    spec = TrustRegionOptions(max_outer=a.spec_max_outer, tcg_max=a.spec_tcg_max, rel_tol=rel)
+    for r in a.r:
+        res = delaunay_study(r, a.k, a.p, a.step, dtype, a.seed, opt, a.save,
+                             log=lambda s: print(s, flush=True), spec_opt=spec)
+        print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,6 +84,20 @@ def edge_uniform(seed: int, lo_id: np.ndarray, hi_id: np.ndarray, lo: float, hi:
     return (lo + (hi - lo) * u).astype(np.float32)
 
 
+def delaunay(n: int, seed: int = SEED_GRAPH) -> Graph:
+    """Delaunay triangulation of n uniform random points in the unit square, unit weights (a
+    stand-in for triangulation graphs: planar, connected, mean degree just under 6)."""
+    from scipy.spatial import Delaunay
+
+    pts = np.random.default_rng(seed).random((n, 2))
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    i = np.concatenate([tri[:, 0], tri[:, 1], tri[:, 2]])
+    j = np.concatenate([tri[:, 1], tri[:, 2], tri[:, 0]])
+    g = csr_from_edges(n, i, j, lambda lo, hi: np.ones(len(lo), dtype=np.float32), name=f"delaunay{n}")
+    g.meta["points"] = pts
+    return g
+
+
 def permute(g: Graph, seed: int) -> Graph:
     """The same graph with node ids relabelled by a seeded random permutation (new id = perm[old]),
     weights carried with their edges; columns ascend within each row of the result."""

@@ -1,5 +1,6 @@
 """Host-side pieces of the driver (CPU only): k-means, RCut, label matching, p schedule."""
 import numpy as np
+import pytest
 
 from paper_2605_26975_amd import driver
 from tests import pins
@@ -39,3 +40,8 @@ def test_p_levels():
     assert driver.p_levels(2.0) == [2.0]
     assert driver.p_levels(1.1) == [2.0, 1.8, 1.6, 1.4, 1.2, 1.1]
     assert driver.p_levels(1.2) == [2.0, 1.8, 1.6, 1.4, 1.2]
+
+
+def test_cluster_rejects_unknown_method():
+    with pytest.raises(ValueError):
+        driver.cluster(None, None, 2, 1.5, method="bfgs")

@@ -127,3 +127,54 @@ def test_cluster_knn_fp32_matches_fp64():
     agree = driver.matched_accuracy(out[torch.float32], out[torch.float64])
     print(f"FP32 vs FP64 label agreement {agree:.5f}")
     assert agree >= 0.99
+
+
+def _laplacian_eigs(g, k):
+    """The k smallest eigenvalues of L = D - W, by a dense symmetric eigensolve (small graphs)."""
+    W = np.zeros((g.n, g.n))
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    W[rows, g.col] = g.w
+    L = np.diag(W.sum(axis=1)) - W
+    return np.linalg.eigvalsh(L)[:k]
+
+
+def test_rtr_p2_reaches_the_laplacian_eigenvalue_sum():
+    """At p = 2 and orthonormal U, F_2(U) = tr(U^T L U) (N sums over ordered pairs), whose minimum on
+    Gr(k, n) is the sum of the k smallest eigenvalues of L (Ky Fan).  The trust-region Newton from a
+    random start must reach it, never go below it, and never increase F."""
+    n, k = 2048, 4
+    g = gen.delaunay(n, seed=3)
+    print(f"[case] rtr delaunay n={n} k={k} p=2", flush=True)
+    lam = _laplacian_eigs(g, k)
+    dg = gu.device_graph(g, k)
+    solver = driver.Solver(dg, k, torch.float64, 1e-8)
+    U0 = driver.orthonormal_start(n, k, 0, torch.float64, "cuda")
+    opt = driver.TrustRegionOptions(max_outer=300, rel_tol=1e-10, tcg_max=300)
+    U, info = driver.rtr(solver, U0, 2.0, opt)
+    F = np.asarray(info.F)
+    print(f"outer {info.iterations} tcg {sum(info.tcg_iterations)} F {F[-1]:.12f} sum(lambda) {lam.sum():.12f}")
+    assert info.grad_norm[-1] <= 1e-10 * info.grad_norm[0]
+    assert np.all(np.diff(F) <= 1e-13 * F[:-1])
+    assert F[-1] >= lam.sum() * (1.0 - 1e-12)
+    assert abs(F[-1] - lam.sum()) <= 1e-8 * lam.sum() + 1e-12
+    # the minimiser spans the eigenspace: U stays orthonormal and L U = U (U^T L U)
+    Uh = U.cpu().numpy()
+    assert np.abs(Uh.T @ Uh - np.eye(k)).max() < 1e-12
+
+
+def test_rtr_continuation_decreases_f_at_each_level():
+    """From the p = 2 minimiser, each smaller p level only accepts steps that lower F_p."""
+    n, k = 4096, 4
+    g = gen.delaunay(n, seed=4)
+    print(f"[case] rtr continuation delaunay n={n} k={k}", flush=True)
+    dg = gu.device_graph(g, k)
+    for dtype in (torch.float32, torch.float64):
+        solver = driver.Solver(dg, k, dtype, 1e-8)
+        U = driver.orthonormal_start(n, k, 0, dtype, "cuda")
+        for pl in (2.0, 1.8, 1.6):
+            U, info = driver.rtr(solver, U, pl, driver.TrustRegionOptions(max_outer=25, rel_tol=1e-6))
+            F = np.asarray(info.F)
+            tol = 1e-6 if dtype == torch.float32 else 1e-13
+            print(f"{dtype} p={pl} outer {info.iterations} F {F[0]:.6f} -> {F[-1]:.6f}")
+            assert np.all(np.diff(F) <= tol * F[:-1])
+            assert F[-1] < F[0]

@@ -72,3 +72,22 @@ def test_permuted_graph_is_the_same_graph(oracle_lib):
     assert np.allclose(Fcp, Fc, rtol=1e-13)
     assert np.allclose(Gp[perm], G, rtol=1e-12, atol=1e-15)
     assert np.allclose(HVp[perm], HV, rtol=1e-12, atol=1e-15)
+
+
+def test_delaunay_generator_is_a_triangulation():
+    """gen.delaunay: symmetric, loop-free, unit weights, connected, and with exactly 3n - 3 - h
+    undirected edges (Euler's formula for a triangulation of n points, h of them on the hull)."""
+    from scipy.spatial import ConvexHull
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    n = 3000
+    g = gen.delaunay(n, seed=5)
+    h = len(ConvexHull(g.meta["points"]).vertices)
+    assert g.nnz == 2 * (3 * n - 3 - h)
+    assert np.all(g.w == 1.0)
+    W = g.to_dense()
+    assert np.array_equal(W, W.T) and np.all(np.diag(W) == 0)
+    A = csr_matrix((g.w, g.col, g.rowptr), shape=(n, n))
+    assert connected_components(A, directed=False)[0] == 1
+    assert 5.9 < g.nnz / n < 6.0
