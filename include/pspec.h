@@ -208,6 +208,32 @@ pspec_status pspec_dot(int64_t n, int k, pspec_dtype dt, const void *A, int64_t 
 pspec_status pspec_axpby(int64_t n, int k, pspec_dtype dt, double alpha, const void *X, int64_t ldx, double beta,
                          void *Y, int64_t ldy, pspec_stream stream);
 
+/*
+ * k-means discretisation (Section 1: the rows of the minimiser U are grouped into clusters by
+ * k-means; the paper does not fix the variant).  One Lloyd step on the rows of the n x d block X:
+ *   labels[i] = the first j minimising dist(i, j) = sum_{t < d} (X[i,t] - C[j,t])^2, the sum taken in
+ *               t order in FP64, each square rounded before it is added (ties go to the lower j);
+ *   dist[i]   = that minimum;
+ *   stats[j * (d + 2) + t] = sum of X[i,t] over the rows i with labels[i] = j      (t < d),
+ *   stats[j * (d + 2) + d] = the number of such rows, stats[j * (d + 2) + d + 1] = the sum of their
+ *               dist (per-cluster inertia).
+ * The next Lloyd centroids are stats[j, t] / stats[j, d].  labels and dist are exact functions of X
+ * and C; stats are FP64 sums in a fixed order, identical from run to run.  X must be finite.
+ *   n           rows (0 is allowed: stats are then zero and labels, dist untouched).
+ *   d, c        columns and clusters, 1..PSPEC_KMEANS_MAX each.
+ *   X           device, n x d (dt), row-major with leading dimension ldx >= d.
+ *   C           device, c x d FP64 centroids, row-major, leading dimension d.
+ *   labels      device, n int32, or NULL;  dist: device, n doubles, or NULL.
+ *   stats       device, c * (d + 2) doubles (REQUIRED).
+ *   ws          device workspace of pspec_kmeans_workspace_bytes(c, d) bytes, 256-byte aligned,
+ *               shared with no other call in flight.
+ */
+#define PSPEC_KMEANS_MAX 32
+size_t pspec_kmeans_workspace_bytes(int c, int d);
+pspec_status pspec_kmeans_step(int64_t n, int d, pspec_dtype dt, const void *X, int64_t ldx, int c, const double *C,
+                               int32_t *labels, double *dist, double *stats, void *ws, size_t ws_bytes,
+                               pspec_stream stream);
+
 /* Message describing the last non-OK status returned on the calling thread ("" if none). */
 const char *pspec_last_error(void);
 

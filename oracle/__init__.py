@@ -19,6 +19,10 @@ spectral clustering with C++ GraphBLAS"):
                        geometry cited in Section 1; the paper prints no formula).
 * ``riemannian_hessian``  P_U(H eta) - eta (U^T G), the Grassmann Hessian of an extrinsic function.
 * ``retract``          qf(U + t eta): the Q factor of the thin QR factorisation with diag(R) > 0.
+* ``kmeans_step``      one Lloyd step of the k-means discretisation of the rows of U (Section 1):
+                       nearest centroid by squared Euclidean distance (coordinates summed in order,
+                       first minimum wins), per-cluster sums, sizes and distance sums.
+* ``lloyd``            Lloyd iterations from given centroids until the centroids stop changing.
 
 Every function's pins live in ``tests/test_oracle.py``.
 """
@@ -199,3 +203,47 @@ def retract(U, eta, t):
     s = np.sign(np.diag(R))
     s[s == 0] = 1.0
     return Q * s[None, :]
+
+
+def kmeans_step(X, C):
+    """Assign every row of X to its nearest centroid (rows of C) and gather the cluster statistics.
+
+    dist[i, j] = sum_t (X[i, t] - C[j, t])^2, accumulated over t in order with each square rounded
+    before it is added; labels = first index of the row minimum.  Returns (labels int32, dist of the
+    chosen centroid, stats) with stats[j] = [sum of the member rows, member count, sum of their dist].
+    """
+    X = np.asarray(X, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    n, d = X.shape
+    c = C.shape[0]
+    D = np.zeros((n, c))
+    for t in range(d):
+        D = D + (X[:, t:t + 1] - C[None, :, t]) ** 2
+    labels = np.argmin(D, axis=1) if n else np.zeros(0, dtype=np.int64)
+    dist = D[np.arange(n), labels]
+    stats = np.zeros((c, d + 2))
+    for j in range(c):
+        m = labels == j
+        stats[j, :d] = X[m].sum(axis=0)
+        stats[j, d] = m.sum()
+        stats[j, d + 1] = dist[m].sum()
+    return labels.astype(np.int32), dist, stats
+
+
+def lloyd(X, C0, iters=100):
+    """Lloyd's k-means from the centroids C0: assign, move every non-empty cluster's centroid to its
+    mean (an empty cluster keeps its centroid), stop when the centroids no longer change.  Returns
+    (labels, centroids, inertia, steps) with labels and inertia taken against the final centroids."""
+    C = np.array(C0, dtype=np.float64)
+    d = C.shape[1]
+    for step in range(1, iters + 1):
+        labels, dist, stats = kmeans_step(X, C)
+        cnt = stats[:, d]
+        Cn = C.copy()
+        nz = cnt > 0
+        Cn[nz] = stats[nz, :d] / cnt[nz, None]
+        if np.array_equal(Cn, C):
+            return labels, C, float(dist.sum()), step
+        C = Cn
+    labels, dist, _ = kmeans_step(X, C)
+    return labels, C, float(dist.sum()), iters

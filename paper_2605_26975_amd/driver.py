@@ -13,7 +13,8 @@ below are this implementation's (see the readings in the design notes):
   actual to model decrease (`rtr`, the default), or followed by Armijo backtracking on
   F(R_U(t eta)) (`Solver.newton`);
 * p-continuation: p = 2.0, 1.8, ... down to the target, each level warm-started;
-* k-means: Lloyd iterations from k-means++ seeds (fixed seed, several restarts) on the rows of U.
+* k-means: Lloyd iterations on the GPU (one pspec_kmeans_step pass per iteration) from k-means++
+  seeds (fixed seed, several restarts) on the rows of U.
 
 Every vector operation (inner products, axpby, projections, retractions, the objective,
 gradient and Hessian-vector products) runs in the HIP library; only FP64 scalars cross to the
@@ -246,34 +247,53 @@ def p_levels(p_target: float, step: float = 0.2) -> list[float]:
     return levels
 
 
-def kmeans(X: np.ndarray, k: int, seed: int = 0, n_init: int = 5, iters: int = 100) -> np.ndarray:
-    """Lloyd's k-means from k-means++ seeds; the restart with the lowest inertia wins."""
-    X = np.asarray(X, dtype=np.float64)
+def lloyd_gpu(X: torch.Tensor, C0: np.ndarray, iters: int = 100):
+    """Lloyd's k-means on the rows of the device block X from the centroids C0 (c x d): every step is
+    one pspec.kmeans_step pass over X; the new centroids (cluster means; an empty cluster keeps its
+    centroid) are formed on the host from the c x (d + 2) statistics.  Stops when the centroids no
+    longer change.  Returns (labels: device int32, centroids: host float64, inertia, steps), labels
+    and inertia taken against the returned centroids."""
+    C = np.array(C0, dtype=np.float64)
+    c, d = C.shape
+    labels = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    stats = torch.empty(c, d + 2, dtype=torch.float64, device=X.device)
+    Cd = torch.empty(c, d, dtype=torch.float64, device=X.device)
+    for step in range(1, iters + 1):
+        Cd.copy_(torch.from_numpy(C))
+        pspec.kmeans_step(X, Cd, labels=labels, stats=stats)
+        st = stats.cpu().numpy()
+        cnt = st[:, d]
+        Cn = C.copy()
+        nz = cnt > 0
+        Cn[nz] = st[nz, :d] / cnt[nz, None]
+        if np.array_equal(Cn, C):
+            return labels, C, float(st[:, d + 1].sum()), step
+        C = Cn
+    Cd.copy_(torch.from_numpy(C))
+    pspec.kmeans_step(X, Cd, labels=labels, stats=stats)
+    return labels, C, float(stats[:, d + 1].sum().item()), iters
+
+
+def kmeans_gpu(X: torch.Tensor, k: int, seed: int = 0, n_init: int = 3, iters: int = 100):
+    """k-means of the rows of the device block X into k clusters: k-means++ seeds (each new seed drawn
+    with probability proportional to the squared distance to the nearest seed so far, the distances
+    from pspec.kmeans_step), then Lloyd iterations on the GPU; of n_init restarts the one with the
+    lowest inertia wins.  Returns (labels: host int64, centroids, inertia)."""
     n = X.shape[0]
     rng = np.random.default_rng(seed)
-    best, best_inertia = None, np.inf
+    dist = torch.empty(n, dtype=torch.float64, device=X.device)
+    best = None
     for _ in range(n_init):
-        C = np.empty((k, X.shape[1]))
-        C[0] = X[rng.integers(n)]
-        d2 = np.sum((X - C[0]) ** 2, axis=1)
-        for c in range(1, k):
-            prob = d2 / d2.sum() if d2.sum() > 0 else np.full(n, 1.0 / n)
-            C[c] = X[rng.choice(n, p=prob)]
-            d2 = np.minimum(d2, np.sum((X - C[c]) ** 2, axis=1))
-        labels = np.zeros(n, dtype=np.int64)
-        for _it in range(iters):
-            dist = np.sum(X * X, axis=1)[:, None] - 2.0 * X @ C.T + np.sum(C * C, axis=1)[None, :]
-            new = np.argmin(dist, axis=1)
-            if _it > 0 and np.array_equal(new, labels):
-                break
-            labels = new
-            for c in range(k):
-                m = labels == c
-                if np.any(m):
-                    C[c] = X[m].mean(axis=0)
-        inertia = float(np.sum((X - C[labels]) ** 2))
-        if inertia < best_inertia:
-            best, best_inertia = labels.copy(), inertia
+        idx = [int(rng.integers(n))]
+        for _c in range(1, k):
+            seeds = X[idx].double().contiguous()
+            pspec.kmeans_step(X, seeds, dist=dist, want_labels=False)
+            d2 = dist.cpu().numpy()
+            tot = d2.sum()
+            idx.append(int(rng.choice(n, p=d2 / tot)) if tot > 0 else int(rng.integers(n)))
+        labels, C, inertia, _ = lloyd_gpu(X, X[idx].double().cpu().numpy(), iters)
+        if best is None or inertia < best[2]:
+            best = (labels.cpu().numpy().astype(np.int64), C, inertia)
     return best
 
 
@@ -319,7 +339,7 @@ def cluster(graph: pspec.Graph, host_graph, k: int, p: float, dtype=torch.float3
         else:
             U, info = solver.newton(U, pl, opt)
         infos.append(info)
-    labels = kmeans(U.double().cpu().numpy(), k, seed=seed)
+    labels, _, _ = kmeans_gpu(U, k, seed=seed)
     return labels, U, infos, rcut(host_graph.rowptr, host_graph.col, host_graph.w, labels)
 
 
@@ -352,7 +372,7 @@ def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t1
         Uh = U.double().cpu().numpy()
-        labels = kmeans(Uh, k, seed=seed, n_init=3)
+        labels, _, _ = kmeans_gpu(U, k, seed=seed)
         lev = {"p": pl, "outer": info.iterations, "tcg": int(sum(info.tcg_iterations)), "F": info.F[-1],
                "grad_rel": info.grad_norm[-1] / info.grad_norm[0], "rcut": rcut(g.rowptr, g.col, g.w, labels),
                "solve_seconds": round(t_solve, 2)}

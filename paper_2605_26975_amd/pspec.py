@@ -52,6 +52,7 @@ def lib() -> ctypes.CDLL:
         "pspec_retract": [i64, i32, i32, vp, i64, vp, i64, dbl, vp, i64, vp, vp, sz, vp],
         "pspec_dot": [i64, i32, i32, vp, i64, vp, i64, vp, vp, sz, vp],
         "pspec_axpby": [i64, i32, i32, dbl, vp, i64, dbl, vp, i64, vp],
+        "pspec_kmeans_step": [i64, i32, i32, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -59,6 +60,8 @@ def lib() -> ctypes.CDLL:
         f.restype = ctypes.c_int
     L.pspec_dense_workspace_bytes.argtypes = [i32]
     L.pspec_dense_workspace_bytes.restype = sz
+    L.pspec_kmeans_workspace_bytes.argtypes = [i32, i32]
+    L.pspec_kmeans_workspace_bytes.restype = sz
     L.pspec_last_error.argtypes = []
     L.pspec_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -71,7 +74,7 @@ def exported_symbols() -> list[str]:
         "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info", "pspec_graph_set_timing_events",
         "pspec_objective", "pspec_grad",
         "pspec_hvp", "pspec_rhvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
-        "pspec_axpby", "pspec_last_error",
+        "pspec_axpby", "pspec_kmeans_workspace_bytes", "pspec_kmeans_step", "pspec_last_error",
     ]
 
 
@@ -283,3 +286,36 @@ def axpby(alpha: float, X: torch.Tensor, beta: float, Y: torch.Tensor) -> torch.
     _check(lib().pspec_axpby(n, k, _dtype_code(Y), float(alpha), X.data_ptr(), _block(X, "X"), float(beta),
                              Y.data_ptr(), _block(Y, "Y"), _stream(Y.device)))
     return Y
+
+
+KMEANS_MAX = 32
+
+
+def kmeans_step(X: torch.Tensor, C: torch.Tensor, labels: torch.Tensor | None = None,
+                dist: torch.Tensor | None = None, stats: torch.Tensor | None = None, want_labels: bool = True):
+    """One Lloyd step on the rows of X (n x d, float32/float64) with FP64 centroids C (c x d):
+    returns (labels int32 [n] or None, dist float64 [n] or None, stats float64 [c, d + 2]) where
+    stats[j] = (coordinate sums of cluster j, its size, its distance sum).  ``dist`` is written only
+    when a tensor is passed."""
+    ldx = _block(X, "X")
+    n, d = X.shape
+    if not (C.is_cuda and C.dtype == torch.float64 and C.dim() == 2 and C.shape[1] == d and C.is_contiguous()):
+        raise ValueError("C must be a contiguous c x d float64 device tensor")
+    c = C.shape[0]
+    if labels is None and want_labels:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    if stats is None:
+        stats = torch.empty(c, d + 2, dtype=torch.float64, device=X.device)
+    for t, name, dt, size in ((labels, "labels", torch.int32, n), (dist, "dist", torch.float64, n),
+                              (stats, "stats", torch.float64, c * (d + 2))):
+        if t is not None and (not t.is_cuda or t.dtype != dt or t.numel() != size or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} device tensor of {size} elements")
+    nbytes = int(lib().pspec_kmeans_workspace_bytes(c, d))
+    key = (str(X.device), "kmeans", c, d)
+    ws = _ws_cache.get(key)
+    if ws is None:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        _ws_cache[key] = ws
+    _check(lib().pspec_kmeans_step(n, d, _dtype_code(X), _ptr(X), ldx, c, _ptr(C), _ptr(labels), _ptr(dist),
+                                   _ptr(stats), _ptr(ws), nbytes, _stream(X.device)))
+    return labels, dist, stats

@@ -94,3 +94,31 @@ def test_rhvp_host_side_errors(libpspec):
     libpspec.pspec_dense_workspace_bytes.argtypes = [i32]
     libpspec.pspec_dense_workspace_bytes.restype = ctypes.c_size_t
     assert libpspec.pspec_dense_workspace_bytes(16) >= 2 * 1024 * 16 * 16 * 8
+
+
+def test_kmeans_host_side_errors(libpspec):
+    """pspec_kmeans_step validates sizes, pointers and the workspace on the host, before any launch;
+    the workspace covers one c x (d + 2) partial per workgroup."""
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    libpspec.pspec_kmeans_step.argtypes = [i64, i32, i32, vp, i64, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    libpspec.pspec_kmeans_step.restype = ctypes.c_int
+    libpspec.pspec_kmeans_workspace_bytes.argtypes = [i32, i32]
+    libpspec.pspec_kmeans_workspace_bytes.restype = ctypes.c_size_t
+    libpspec.pspec_last_error.restype = ctypes.c_char_p
+    ws = libpspec.pspec_kmeans_workspace_bytes(4, 4)
+    assert ws >= 1024 * 4 * 6 * 8
+    call = libpspec.pspec_kmeans_step
+    # (n, d, dt, X, ldx, c, C, labels, dist, stats, ws, ws_bytes, stream)
+    assert call(-1, 4, 0, 256, 4, 4, 512, None, None, 768, 1024, ws, None) == 1
+    assert call(100, 0, 0, 256, 4, 4, 512, None, None, 768, 1024, ws, None) == 1
+    assert call(100, 33, 0, 256, 33, 4, 512, None, None, 768, 1024, 1 << 30, None) == 2
+    assert call(100, 4, 0, 256, 4, 0, 512, None, None, 768, 1024, ws, None) == 1
+    assert call(100, 4, 0, 256, 4, 33, 512, None, None, 768, 1024, 1 << 30, None) == 2
+    assert call(100, 4, 0, 256, 3, 4, 512, None, None, 768, 1024, ws, None) == 1
+    assert b"ldx" in libpspec.pspec_last_error()
+    assert call(100, 4, 0, None, 4, 4, 512, None, None, 768, 1024, ws, None) == 1
+    assert call(100, 4, 0, 256, 4, 4, None, None, None, 768, 1024, ws, None) == 1
+    assert call(100, 4, 0, 256, 4, 4, 512, None, None, None, 1024, ws, None) == 1
+    assert call(100, 4, 0, 256, 4, 4, 512, None, None, 768, 1000, ws, None) == 1
+    assert call(100, 4, 0, 256, 4, 4, 512, None, None, 768, 1024, ws - 8, None) == 4
+    assert b"workspace" in libpspec.pspec_last_error()

@@ -1,4 +1,4 @@
-"""Host-side pieces of the driver (CPU only): k-means, RCut, label matching, p schedule."""
+"""Host-side pieces of the driver (CPU only): RCut, label matching, p schedule."""
 import numpy as np
 import pytest
 
@@ -17,15 +17,6 @@ def test_rcut_hand_example():
     assert abs(driver.rcut(rp, c, w, np.array([0, 0, 0, 1, 1, 1])) - 1.0 / 3.0) < 1e-15
     # a worse split: {0,1} vs the rest -> cut = w02 + w12 = 2, RCut = 2/2 + 2/4
     assert abs(driver.rcut(rp, c, w, np.array([0, 0, 1, 1, 1, 1])) - 1.5) < 1e-15
-
-
-def test_kmeans_separated_blobs():
-    rng = np.random.default_rng(0)
-    centres = np.array([[0, 0], [10, 0], [0, 10], [10, 10]], dtype=float)
-    truth = np.repeat(np.arange(4), 200)
-    X = centres[truth] + rng.standard_normal((800, 2))
-    labels = driver.kmeans(X, 4, seed=3)
-    assert driver.matched_accuracy(labels, truth) == 1.0
 
 
 def test_matched_accuracy_is_permutation_invariant():

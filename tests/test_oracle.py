@@ -91,3 +91,55 @@ def test_delaunay_generator_is_a_triangulation():
     A = csr_matrix((g.w, g.col, g.rowptr), shape=(n, n))
     assert connected_components(A, directed=False)[0] == 1
     assert 5.9 < g.nnz / n < 6.0
+
+
+def test_kmeans_step_pins():
+    """orc.kmeans_step against facts that do not depend on it: rows placed on a centroid get that
+    centroid at distance 0; in 1-D the nearest of sorted centroids is fixed by the midpoints between
+    them (ties at a midpoint go to the lower index); member sums and counts add up to the column sums
+    and n; per-cluster inertia obeys the parallel-axis identity sum ||x - c||^2 = sum ||x - m||^2 +
+    n_j ||m - c||^2 about the cluster mean m; distances equal squared norms from numpy.linalg."""
+    rng = np.random.default_rng(11)
+    C = rng.normal(size=(5, 3))
+    X = np.repeat(C, 4, axis=0)[rng.permutation(20)]
+    lab, dist, stats = orc.kmeans_step(X, C)
+    assert np.array_equal(C[lab], X) and np.all(dist == 0.0)
+    assert np.array_equal(stats[:, 3], np.full(5, 4.0))
+    # 1-D: midpoints
+    c1 = np.array([[-1.0], [0.5], [2.0], [7.0]])
+    x1 = np.concatenate([rng.uniform(-4, 10, 500), [-0.25, 1.25, 4.5]])[:, None]  # last three: exact ties
+    lab1, _, _ = orc.kmeans_step(x1, c1)
+    mids = (c1[1:, 0] + c1[:-1, 0]) / 2
+    assert np.array_equal(lab1, np.searchsorted(mids, x1[:, 0], side="left"))
+    # reordering the centroids relabels the rows the same way (away from the exact ties, whose
+    # winner is the lower index and so depends on the order)
+    perm = np.array([2, 0, 3, 1])
+    lab1p, _, _ = orc.kmeans_step(x1, c1[perm])
+    assert np.array_equal(perm[lab1p][:500], lab1[:500])
+    # general data: conservation, parallel axis, brute-force distances
+    X = rng.normal(size=(400, 6))
+    C = rng.normal(size=(7, 6))
+    lab, dist, stats = orc.kmeans_step(X, C)
+    assert np.allclose(stats[:, :6].sum(axis=0), X.sum(axis=0), rtol=0, atol=1e-12)
+    assert stats[:, 6].sum() == 400
+    full = np.linalg.norm(X[:, None, :] - C[None, :, :], axis=2) ** 2
+    assert np.array_equal(lab, np.argmin(full, axis=1))
+    assert np.allclose(dist, full.min(axis=1), rtol=1e-14)
+    for j in range(7):
+        m = lab == j
+        if m.sum() == 0:
+            continue
+        mean = X[m].mean(axis=0)
+        pa = ((X[m] - mean) ** 2).sum() + m.sum() * ((mean - C[j]) ** 2).sum()
+        assert abs(stats[j, 7] - pa) <= 1e-12 * pa
+
+
+def test_lloyd_hand_example():
+    """Two well separated pairs in 1-D, started from two points of the first pair: step 1 sends 0 to
+    c0 = 0 and 1, 10, 11 to c1 = 1, moving c1 to 22/3; step 2 forms {0, 1} and {10, 11}, moving the
+    centroids to 0.5 and 10.5; step 3 changes nothing.  Inertia 4 * 0.25 = 1."""
+    X = np.array([[0.0], [1.0], [10.0], [11.0]])
+    lab, C, inertia, steps = orc.lloyd(X, np.array([[0.0], [1.0]]))
+    assert np.array_equal(lab, [0, 0, 1, 1])
+    assert np.array_equal(C[:, 0], [0.5, 10.5])
+    assert inertia == 1.0 and steps == 3
