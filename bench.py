@@ -328,20 +328,26 @@ def main() -> int:
 
     def extras(reps: int = 10):
         """FP32 side measurements (not the metric): each call of the step on its own, the unfused
-        pspec_hvp call (edge pass + epilogue), the edge pass with the Infinity Cache flushed before
-        every run, and a streaming-read reference rate of this GPU (pspec_dot over 2 GiB)."""
+        pspec_hvp call (edge pass + epilogue), one k-means step on U's rows (k clusters) with its
+        algorithmic rate, the edge pass with the Infinity Cache flushed before every run, and a
+        streaming-read reference rate of this GPU (pspec_dot over 2 GiB)."""
         dtype = torch.float32
         U, V, keep = make_inputs(dtype)
         RG, RH, Un, HV, G = (torch.empty((n, k), dtype=dtype, device=dev) for _ in range(5))
         MG = torch.empty((k, k), dtype=torch.float64, device=dev)
         Fc = torch.empty(k, dtype=torch.float64, device=dev)
         F = torch.empty((), dtype=torch.float64, device=dev)
+        # one Lloyd step of the k-means discretisation of U's rows into k clusters (labels written)
+        Ck = U[:k].double().contiguous()
+        lab = torch.empty(n, dtype=torch.int32, device=dev)
+        st = torch.empty((k, k + 2), dtype=torch.float64, device=dev)
         calls = {
             "rhvp": lambda: pspec.rhvp(dg, U, V, p, eps, RH=RH, RG=RG, MG=MG, F_col=Fc),
             "hvp": lambda: pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc),
             "project": lambda: pspec.project(U, G, out=RG, M=MG),
             "retract": lambda: pspec.retract(U, RG, -1e-3, out=Un),
             "objective": lambda: pspec.objective(dg, Un, p, F_col=Fc, F=F),
+            "kmeans_step": lambda: pspec.kmeans_step(U, Ck, labels=lab, stats=st),
         }
         ms = {}
         for name, fn in calls.items():
@@ -384,6 +390,7 @@ def main() -> int:
             "call_ms": ms,
             "hvp_call_value": nnz * k / (ms["hvp"] * 1e-3),
             "edge_pass_cold_ms": float(np.mean(cold)),
+            "kmeans_step_GBps": (n * k * U.element_size() + 4 * n) / (ms["kmeans_step"] * 1e-3) / 1e9,
             "read_stream_GBps": read_gbs,
         }
 

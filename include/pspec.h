@@ -106,6 +106,20 @@ pspec_status pspec_graph_destroy(pspec_graph g);
 pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int64_t *chunks, int64_t *split_rows);
 
 /*
+ * pspec_rcm_order -- a locality relabelling of the graph for the edge pass (the vxm of Section 2
+ * gathers one neighbour row per edge; graphs numbered without locality, such as triangulations of
+ * random points, make every gather a cache miss).  Reverse Cuthill-McKee: per connected component
+ * a breadth-first sweep from a pseudo-peripheral node (George-Liu), unvisited neighbours taken in
+ * increasing (degree, id), components in increasing (degree, id) of their first node, the whole
+ * sequence reversed.  Writes perm[old id] = new id (a permutation of 0..n-1).  Host code: rowptr
+ * (n + 1), col (rowptr[n]) and perm (n) are HOST arrays; the graph must be symmetric (the order is
+ * valid for any graph, its locality only for symmetric ones).  The caller relabels the CSR and the
+ * rows of U once and solves in the new order; nothing in the library applies it.  Invalid CSR
+ * returns PSPEC_ERR_ARG.  O(nnz log(max degree)) time, O(n) extra memory.
+ */
+pspec_status pspec_rcm_order(int64_t n, const int64_t *rowptr, const int32_t *col, int64_t *perm);
+
+/*
  * Timing hook (for benchmarks).  While set, every pspec_objective / pspec_grad / pspec_hvp call on
  * this handle records `before` on its stream immediately before the first kernel of the edge pass
  * and `after` immediately after its last one (light rows, heavy chunks, split-row combine), so
@@ -148,6 +162,18 @@ pspec_status pspec_grad(pspec_graph g, pspec_dtype dt, int k, const void *U, int
 pspec_status pspec_hvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
                        int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
                        double *F_col, pspec_stream stream);
+
+/*
+ * pspec_hvp_sparse -- pspec_hvp with the Hessian restricted to its sparse part, the reading of
+ * Algorithm 1 in which D[l] = diag(H^l) and H[l] = diag(H^l) - H^l are GraphBLAS matrices with the
+ * sparsity of the graph: HV = (p/D)((p - 1) J - F (p - 1) psi(u) v), i.e. the exact Hessian-vector
+ * product without its dense rank-2 part -(p/D)(g phi^T + phi g^T) v.  G, F_col, arguments, layout
+ * and errors are those of pspec_hvp (G is the exact gradient).  For comparison with the paper's
+ * formulation; Newton on this operator is an inexact Newton method.
+ */
+pspec_status pspec_hvp_sparse(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                              int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
+                              double *F_col, pspec_stream stream);
 
 /*
  * Dense n x k operations of the Grassmann geometry (the manifold of Section 2; the formulas are

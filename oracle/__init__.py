@@ -14,6 +14,8 @@ spectral clustering with C++ GraphBLAS"):
 * ``grad``             the EucGrad callback of Section 2: the gradient of Eq. (1), derived by calculus.
 * ``hvp``              the EucHessianEta callback of Section 2 / Algorithm 1: the exact Hessian of
                        Eq. (1) applied per column, |x|^(p-2) capped at eps^(p-2) near x = 0.
+* ``hvp_sparse``       Algorithm 1 read with sparse matrices D[l], H[l]: the Hessian without its
+                       dense rank-2 part, i.e. (p/D) times the derivative of Delta_p u - F phi_p(u).
 * ``brute_objective``  Eq. (1) literally: a double loop over all ordered node pairs of a dense W.
 * ``project``          Grassmann tangent projection P_U(Z) = Z - U (U^T Z) (Edelman, Arias, Smith
                        geometry cited in Section 1; the paper prints no formula).
@@ -76,6 +78,9 @@ class Oracle:
         lib.oracle_hvp.argtypes = [_i64, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _i64, _f64p, _i64,
                                    _dbl, _dbl, _f64p, opt, opt]
         lib.oracle_hvp.restype = None
+        lib.oracle_hvp_sparse.argtypes = [_i64, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _i64, _f64p, _i64,
+                                          _dbl, _dbl, _f64p]
+        lib.oracle_hvp_sparse.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         self.lib = lib
@@ -148,6 +153,20 @@ class Oracle:
         self.lib.oracle_hvp(n, rowptr, col, w, k, U, k, V, k, float(p), float(eps), HV, G.ctypes.data,
                             Fc.ctypes.data)
         return HV, G, Fc
+
+    def hvp_sparse(self, rowptr, col, w, U, V, p, eps):
+        """The sparse part of the Hessian at U applied to V: the derivative of (p/D)(Delta_p u - F phi_p(u))
+        along V with D and F held fixed (the exact Hessian without its rank-2 term)."""
+        rowptr, col, w = self._csr(rowptr, col, w)
+        n = len(rowptr) - 1
+        U = self._block(U, n)
+        V = self._block(V, n)
+        k = U.shape[1]
+        if V.shape[1] != k:
+            raise ValueError("U and V differ in k")
+        HV = np.zeros_like(U)
+        self.lib.oracle_hvp_sparse(n, rowptr, col, w, k, U, k, V, k, float(p), float(eps), HV)
+        return HV
 
 
 _default: Oracle | None = None

@@ -202,6 +202,35 @@ void oracle_hvp(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
     free(b);
 }
 
+/* The sparse part of the Hessian applied to V (the exact operator of oracle_hvp without its rank-2
+ * term): HV = (p/D) (J_L v - F J_phi v), J_L v = (p-1) sum_j w psi(u_i - u_j)(v_i - v_j),
+ * J_phi v = (p-1) psi(u_i) v_i, the derivatives of the p-Laplacian and of phi_p along v. */
+void oracle_hvp_sparse(int64_t n, const int64_t *rowptr, const int32_t *col, const double *w,
+                       int k, const double *U, int64_t ldu, const double *V, int64_t ldv,
+                       double p, double eps, double *HV)
+{
+    double *D = (double *)malloc(sizeof(double) * (size_t)k);
+    double *Fl = (double *)malloc(sizeof(double) * (size_t)k);
+    oracle_objective(n, rowptr, col, w, k, U, ldu, p, NULL, D, Fl, NULL);
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 512)
+    for (i = 0; i < n; ++i) {
+        for (int l = 0; l < k; ++l) {
+            double ui = U[i * ldu + l], vi = V[i * ldv + l];
+            long double s = 0.0L;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                int64_t j = col[e];
+                s += (long double)(w[e] * psi_eps(ui - U[j * ldu + l], p, eps) * (vi - V[j * ldv + l]));
+            }
+            double JL = (p - 1.0) * (double)s;
+            double Jphi = (p - 1.0) * psi_eps(ui, p, eps) * vi;
+            HV[i * k + l] = (p / D[l]) * (JL - Fl[l] * Jphi);
+        }
+    }
+    free(D);
+    free(Fl);
+}
+
 /* Number of OpenMP threads a parallel region of this library uses (1 without OpenMP). */
 int oracle_num_threads(void)
 {

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpspec.so")
-SOURCES = ["graph.hip", "edge.hip", "dense.hip", "kmeans.hip"]
+SOURCES = ["graph.hip", "edge.hip", "dense.hip", "kmeans.hip", "order.hip"]
 ARCH = "gfx950"
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in generated code.

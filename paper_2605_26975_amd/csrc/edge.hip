@@ -28,7 +28,14 @@ namespace {
 enum Mode { OBJ = 0, GRAD = 1, HVP = 2 };
 
 // |x|^(p-2) for x >= 0.  FP32: hardware exp2/log2 on max(x, 2^-64), so an exact zero gives a finite
-// value (2^(64 (2-p))) whose product with x is exactly 0.  FP64: the device-library pow().
+// value (2^(64 (2-p))) whose product with x is exactly 0.  FP64: exp(q ln x) for x clamped to
+// [2^-512, inf), q = p - 2, written out for this one use (the general pow() handles cases that
+// cannot occur here and costs several times as many instructions, which bounds the FP64 edge pass):
+//   x = 2^e m, m in [1/sqrt 2, sqrt 2);  ln m = 2 atanh(s), s = (m - 1)/(m + 1), by the odd series
+//   sum s^(2j+1)/(2j+1) to j = 11 (|s| <= 0.172: truncation below 2^-60);  ln x = e ln 2 + ln m and
+//   t = q ln x as double-doubles (ln 2 split so that e ln2_hi is exact);  exp(t) = 2^n exp(r),
+//   n = rint(t / ln 2), |r| <= ln 2 / 2, exp(r) by its Taylor series to r^13 (truncation below
+//   2^-57).  A few units in the last place; q = 0 gives exactly 1; x = inf gives pow()'s limits.
 template <typename T>
 struct PowM2;
 template <>
@@ -42,7 +49,58 @@ struct PowM2<float> {
 template <>
 struct PowM2<double> {
     double pm2;
-    __device__ __forceinline__ double operator()(double ax) const { return pow(fmax(ax, 0x1p-512), pm2); }
+    __device__ __forceinline__ double operator()(double ax) const {
+        constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;  // ln 2 to 42 bits: e * kLn2Hi is exact
+        constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
+        constexpr double kLog2e = 0x1.71547652b82fep0;
+        const double x = fmax(ax, 0x1p-512);
+        int e;
+        double m = frexp(x, &e);  // [1/2, 1)
+        const bool low = m < 0x1.6a09e667f3bcdp-1;
+        m = low ? 2.0 * m : m;
+        e = low ? e - 1 : e;
+        const double f = m - 1.0;  // exact
+        const double sv = f / (f + 2.0);
+        const double R = sv * sv;
+        double P = 1.0 / 23.0;
+        P = fma(P, R, 1.0 / 21.0);
+        P = fma(P, R, 1.0 / 19.0);
+        P = fma(P, R, 1.0 / 17.0);
+        P = fma(P, R, 1.0 / 15.0);
+        P = fma(P, R, 1.0 / 13.0);
+        P = fma(P, R, 1.0 / 11.0);
+        P = fma(P, R, 1.0 / 9.0);
+        P = fma(P, R, 1.0 / 7.0);
+        P = fma(P, R, 1.0 / 5.0);
+        P = fma(P, R, 1.0 / 3.0);
+        const double lnm = fma(2.0 * sv, R * P, 2.0 * sv);  // 2 s (1 + R P)
+        const double de = (double)e;
+        const double a = de * kLn2Hi;                        // exact; |a| > |ln m| unless e = 0
+        const double hi = a + lnm;
+        const double lo = ((a - hi) + lnm) + de * kLn2Lo;
+        const double th = pm2 * hi;
+        const double tl = fma(pm2, hi, -th) + pm2 * lo;
+        const double n = rint(th * kLog2e);
+        double r = fma(-n, kLn2Hi, th);
+        r = fma(-n, kLn2Lo, r) + tl;
+        double E = 1.0 / 6227020800.0;  // 1/13!
+        E = fma(E, r, 1.0 / 479001600.0);
+        E = fma(E, r, 1.0 / 39916800.0);
+        E = fma(E, r, 1.0 / 3628800.0);
+        E = fma(E, r, 1.0 / 362880.0);
+        E = fma(E, r, 1.0 / 40320.0);
+        E = fma(E, r, 1.0 / 5040.0);
+        E = fma(E, r, 1.0 / 720.0);
+        E = fma(E, r, 1.0 / 120.0);
+        E = fma(E, r, 1.0 / 24.0);
+        E = fma(E, r, 1.0 / 6.0);
+        E = fma(E, r, 0.5);
+        E = fma(E, r, 1.0);
+        E = fma(E, r, 1.0);
+        const double y = ldexp(E, (int)n);
+        // x = inf (a non-finite U): the limits of pow (0, 1 or inf by the sign of q); NaN stays NaN
+        return x < __builtin_inf() ? y : (pm2 < 0.0 ? 0.0 : (pm2 == 0.0 ? 1.0 : x));
+    }
 };
 
 template <typename T, typename WT>
@@ -515,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void reduce_stage1(const double *__restrict
 // Stage 2 (one workgroup): totals and the per-column scalars.
 __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict__ red1, int W, int k, double p,
                                                       double *__restrict__ sc, int k_max, double *__restrict__ F_col,
-                                                      double *__restrict__ F) {
+                                                      double *__restrict__ F, bool rank2) {
     __shared__ double s[kBlock];
     __shared__ double sf[PSPEC_K_MAX];
     const int tid = threadIdx.x;
@@ -532,8 +590,9 @@ __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict
         sc[SC_D * k_max + tid] = D;
         sc[SC_F * k_max + tid] = Fl;
         sc[SC_PD * k_max + tid] = pD;
-        sc[SC_A * k_max + tid] = av;
-        sc[SC_B * k_max + tid] = pD * (S - Fl * av);
+        // without the rank-2 part of the Hessian the epilogue's g a + phi b term is zero
+        sc[SC_A * k_max + tid] = rank2 ? av : 0.0;
+        sc[SC_B * k_max + tid] = rank2 ? pD * (S - Fl * av) : 0.0;
         sf[tid] = Fl;
         if (F_col) F_col[tid] = Fl;
     }
@@ -783,7 +842,7 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
 // scalars; L and J receive the raw rows.
 template <typename T, typename WT, int K, int MODE>
 pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J, int64_t ldj,
-               double p, double eps, double *F_col, double *F, hipStream_t s) {
+               double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2 = true) {
     EdgeArgs<T, WT> a;
     a.rowptr = g->rowptr;
     a.col = g->col;
@@ -818,14 +877,14 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     if (g->ev_after) PSPEC_HIP(hipEventRecord(g->ev_after, s));
     const int W = kQ * k;
     reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + hb, W, g->red1);
-    reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F);
+    reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F, rank2);
     return PSPEC_OK;
 }
 
 template <typename T, typename WT, int K, int MODE>
 pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J,
-                          int64_t ldj, double p, double eps, double *F_col, double *F, hipStream_t s) {
-    const pspec_status st = edge_pass<T, WT, K, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
+                          int64_t ldj, double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2) {
+    const pspec_status st = edge_pass<T, WT, K, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s, rank2);
     if (st != PSPEC_OK) return st;
     if (MODE != OBJ) {
         PowM2<T> pw;
@@ -838,10 +897,13 @@ pspec_status launch_edges(Graph *g, int k, const T *U, int64_t ldu, const T *V, 
     return PSPEC_OK;
 }
 
-// The fused kernels run on the matrix cores up to k = 32; wider blocks take the stand-alone path.
+// The fused kernels run on the matrix cores for 16 <= k <= 32.  Below 16 the matrix-core layout pads
+// the rows to 16 columns, so the two fused kernels would evaluate the epilogue (one power per
+// entry, a long FP64 routine in the FP64 path) for the padding lanes too, and twice per entry; the
+// stand-alone sequence evaluates it once per entry.  Wider blocks take the stand-alone path as well.
 template <typename T, int K>
 constexpr bool rhvp_fused() {
-    return K <= 32;
+    return K >= 16 && K <= 32;
 }
 
 // Riemannian gradient and Hessian-vector product on Gr(k, n).  Workspace: level-1 partials
@@ -887,13 +949,13 @@ pspec_status launch_rhvp(Graph *g, int k, const T *U, int64_t ldu, const T *V, i
 
 template <typename T, typename WT, int MODE>
 pspec_status dispatch_k(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J,
-                        int64_t ldj, double p, double eps, double *F_col, double *F, hipStream_t s) {
+                        int64_t ldj, double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2) {
     switch (pad_k(k)) {
-        case 4: return launch_edges<T, WT, 4, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
-        case 8: return launch_edges<T, WT, 8, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
-        case 16: return launch_edges<T, WT, 16, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
-        case 32: return launch_edges<T, WT, 32, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
-        case 64: return launch_edges<T, WT, 64, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s);
+        case 4: return launch_edges<T, WT, 4, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s, rank2);
+        case 8: return launch_edges<T, WT, 8, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s, rank2);
+        case 16: return launch_edges<T, WT, 16, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s, rank2);
+        case 32: return launch_edges<T, WT, 32, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s, rank2);
+        case 64: return launch_edges<T, WT, 64, MODE>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, p, eps, F_col, F, s, rank2);
         default: set_error("unsupported k = %d", k); return PSPEC_ERR_UNSUPPORTED;
     }
 }
@@ -901,15 +963,15 @@ pspec_status dispatch_k(Graph *g, int k, const T *U, int64_t ldu, const T *V, in
 template <int MODE>
 pspec_status dispatch(Graph *g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V, int64_t ldv,
                       void *L, int64_t ldl, void *J, int64_t ldj, double p, double eps, double *F_col, double *F,
-                      hipStream_t s) {
+                      hipStream_t s, bool rank2 = true) {
     if (dt == PSPEC_F32)
         return dispatch_k<float, float, MODE>(g, k, (const float *)U, ldu, (const float *)V, ldv, (float *)L, ldl,
-                                              (float *)J, ldj, p, eps, F_col, F, s);
+                                              (float *)J, ldj, p, eps, F_col, F, s, rank2);
     if (g->wtype == PSPEC_F32)
         return dispatch_k<double, float, MODE>(g, k, (const double *)U, ldu, (const double *)V, ldv, (double *)L,
-                                               ldl, (double *)J, ldj, p, eps, F_col, F, s);
+                                               ldl, (double *)J, ldj, p, eps, F_col, F, s, rank2);
     return dispatch_k<double, double, MODE>(g, k, (const double *)U, ldu, (const double *)V, ldv, (double *)L, ldl,
-                                            (double *)J, ldj, p, eps, F_col, F, s);
+                                            (double *)J, ldj, p, eps, F_col, F, s, rank2);
 }
 
 template <typename T, typename WT, int K>
@@ -991,24 +1053,36 @@ extern "C" pspec_status pspec_grad(pspec_graph g, pspec_dtype dt, int k, const v
                           reinterpret_cast<hipStream_t>(stream));
 }
 
-extern "C" pspec_status pspec_hvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
-                                  int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
-                                  double *F_col, pspec_stream stream) {
+static pspec_status hvp_entry(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                              int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
+                              double *F_col, pspec_stream stream, bool rank2, const char *who) {
     clear_error();
-    pspec_status st = check_common(g, dt, k, U, ldu, p, "hvp");
+    pspec_status st = check_common(g, dt, k, U, ldu, p, who);
     if (st != PSPEC_OK) return st;
-    PSPEC_ARG(eps > 0.0 && std::isfinite(eps), "hvp: eps = %g must be positive", eps);
-    if ((st = check_out(g, dt, k, V, ldv, "V", "hvp")) != PSPEC_OK) return st;
-    if ((st = check_out(g, dt, k, HV, ldh, "HV", "hvp")) != PSPEC_OK) return st;
-    if ((st = check_out(g, dt, k, G, ldg, "G", "hvp")) != PSPEC_OK) return st;
+    PSPEC_ARG(eps > 0.0 && std::isfinite(eps), "%s: eps = %g must be positive", who, eps);
+    if ((st = check_out(g, dt, k, V, ldv, "V", who)) != PSPEC_OK) return st;
+    if ((st = check_out(g, dt, k, HV, ldh, "HV", who)) != PSPEC_OK) return st;
+    if ((st = check_out(g, dt, k, G, ldg, "G", who)) != PSPEC_OK) return st;
     const size_t es = dt == PSPEC_F32 ? 4 : 8;
     const int64_t n = g->n;
     PSPEC_ARG(!blocks_overlap(HV, ldh, U, ldu, n, k, es) && !blocks_overlap(HV, ldh, V, ldv, n, k, es) &&
                   !blocks_overlap(G, ldg, U, ldu, n, k, es) && !blocks_overlap(G, ldg, V, ldv, n, k, es) &&
                   !blocks_overlap(G, ldg, HV, ldh, n, k, es),
-              "hvp: HV and G must not overlap U, V or each other");
+              "%s: HV and G must not overlap U, V or each other", who);
     return dispatch<HVP>(g, dt, k, U, ldu, V, ldv, G, ldg, HV, ldh, p, eps, F_col, nullptr,
-                         reinterpret_cast<hipStream_t>(stream));
+                         reinterpret_cast<hipStream_t>(stream), rank2);
+}
+
+extern "C" pspec_status pspec_hvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                                  int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
+                                  double *F_col, pspec_stream stream) {
+    return hvp_entry(g, dt, k, U, ldu, V, ldv, p, eps, HV, ldh, G, ldg, F_col, stream, true, "hvp");
+}
+
+extern "C" pspec_status pspec_hvp_sparse(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu,
+                                         const void *V, int64_t ldv, double p, double eps, void *HV, int64_t ldh,
+                                         void *G, int64_t ldg, double *F_col, pspec_stream stream) {
+    return hvp_entry(g, dt, k, U, ldu, V, ldv, p, eps, HV, ldh, G, ldg, F_col, stream, false, "hvp_sparse");
 }
 
 extern "C" pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,

@@ -5,10 +5,10 @@
 // centroid as sum_t (x_t - c_t)^2 in t order with no fused multiply-add, and keeps the first
 // centroid of smallest distance, so labels and distances are a plain function of the inputs (no
 // summation order to choose).  The per-cluster statistics (coordinate sums, count, distance sum) of
-// each 64-row wave batch are reduced across the wave by an xor butterfly and accumulated, cluster j
-// in lane j, in wave order; the four waves of a workgroup are added in order into one partial per
-// workgroup, and the kDenseBlocks partials are added by the fixed two-level tree of the dense
-// kernels.  The statistics are therefore bit-reproducible from run to run.  The work is one read of
+// each 64-row wave batch are reduced across the wave (DPP exchanges within 16-lane rows, then the
+// four row sums; no LDS traffic) and accumulated, cluster j in lane j, in wave order; the four waves
+// of a workgroup are added in order into one partial per workgroup, and the kDenseBlocks partials
+// are added by the fixed two-level tree of the dense kernels.  The statistics are therefore bit-reproducible from run to run.  The work is one read of
 // the block (plus the optional label and distance writes): HBM bound for the d and c of clustering U.
 #include "common.hpp"
 #include "dense.hpp"
@@ -33,11 +33,29 @@ __device__ __forceinline__ double sqdist(const double (&x)[D], const double *cj)
     return s;
 }
 
-// Sum over the 64 lanes by an xor butterfly; every lane ends with the same value.
+// One DPP lane exchange of a double (two 32-bit moves, VALU only).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes in a fixed order, the same value in every lane: within each 16-lane row,
+// partners exchanged by DPP (lanes i and i^1, then i^2, then i and 7-i within each half row, then i
+// and 15-i; each step adds two equal-sized partial sums, and since addition commutes both partners
+// hold the same result), then the four row sums read from lanes 0, 16, 32, 48.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 template <typename T, int D, bool VEC>

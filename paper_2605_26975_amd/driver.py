@@ -54,14 +54,20 @@ class NewtonInfo:
 class Solver:
     """Work buffers and the Newton-tCG iteration for one graph, k and dtype."""
 
-    def __init__(self, graph: pspec.Graph, k: int, dtype=torch.float32, eps: float = 1e-8):
-        self.graph, self.k, self.dtype, self.eps = graph, k, dtype, eps
+    def __init__(self, graph: pspec.Graph, k: int, dtype=torch.float32, eps: float = 1e-8,
+                 hessian: str = "exact"):
+        """``hessian``: "exact" (the Hessian of Eq. (1)) or "sparse" (without its rank-2 part: Algorithm 1
+        read with sparse D[l], H[l]; Newton then solves an approximate system)."""
+        if hessian not in ("exact", "sparse"):
+            raise ValueError(f"unknown hessian {hessian!r}")
+        self.graph, self.k, self.dtype, self.eps, self.hessian = graph, k, dtype, eps, hessian
         n = graph.n
         dev = graph.device
         mk = lambda: torch.empty((n, k), dtype=dtype, device=dev)  # noqa: E731
         self.G, self.HV, self.rgrad = mk(), mk(), mk()
         self.eta, self.r, self.delta, self.Hd, self.Ut = mk(), mk(), mk(), mk(), mk()
         self.MG = torch.empty((k, k), dtype=torch.float64, device=dev)
+        self.Hd2 = mk() if hessian == "sparse" else None
 
     # --- small wrappers (each a library call) -------------------------------------------------
     def F(self, U, p) -> float:
@@ -75,7 +81,13 @@ class Solver:
         """Riemannian Hessian at U applied to the tangent vector X: one fused library call (edge
         pass, epilogue, both Gram matrices and the projection); the Riemannian gradient it also
         returns goes to a scratch block."""
-        pspec.rhvp(self.graph, U, X, p, self.eps, RH=out, RG=self.HV, MG=self.MG)
+        if self.hessian == "exact":
+            pspec.rhvp(self.graph, U, X, p, self.eps, RH=out, RG=self.HV, MG=self.MG)
+            return out
+        # sparse-only operator: Euclidean product, then P_U(H X) - X (U^T G)
+        pspec.hvp(self.graph, U, X, p, self.eps, HV=self.HV, G=self.G, sparse_only=True)
+        pspec.project(U, self.G, out=self.Hd2, M=self.MG)
+        pspec.project(U, self.HV, X=X, MX=self.MG, out=out)
         return out
 
     def newton(self, U: torch.Tensor, p: float, opt: NewtonOptions | None = None) -> tuple[torch.Tensor, NewtonInfo]:
@@ -152,11 +164,12 @@ class TrustRegionOptions:
     delta0: float | None = None     # first radius (default delta_bar / 8)
 
 
-def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | None = None):
+def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | None = None, progress=None):
     """Riemannian trust-region Newton on Gr(k, n) (Absil, Baker and Gallivan's RTR, the method behind
     the paper's Newton / truncated-CG solver): the Newton system is solved by Steihaug-Toint
     truncated CG inside a ball of radius Delta, the step is accepted by the ratio rho of actual to
-    model decrease, and Delta shrinks or grows with rho.  Returns the final U and a log."""
+    model decrease, and Delta shrinks or grows with rho.  ``progress(it, F, |grad|, tCG steps)`` is
+    called after every outer iteration when given.  Returns the final U and a log."""
     opt = opt or TrustRegionOptions()
     s = solver
     k = s.k
@@ -224,6 +237,8 @@ def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | Non
         if rho > opt.rho_accept:
             pspec.axpby(1.0, s.Ut, 0.0, U)
         info.iterations = it + 1
+        if progress is not None:
+            progress(it + 1, Fu, gn, nt)
     return U, info
 
 
@@ -345,30 +360,46 @@ def cluster(graph: pspec.Graph, host_graph, k: int, p: float, dtype=torch.float3
 
 def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=torch.float64,
                    seed: int = 0, opt: TrustRegionOptions | None = None, save: str | None = None,
-                   log=print, spec_opt: TrustRegionOptions | None = None) -> dict:
+                   log=print, spec_opt: TrustRegionOptions | None = None, order: str = "rcm") -> dict:
     """The whole pipeline on a Delaunay graph of 2^r uniform random points (the stand-in for the
     paper's triangulation matrices, Section 3): trust-region Newton at each p level of the
     continuation, k-means on the rows of U and RCut after every level.  The p = 2 level is the
     spectral (Spec) solution the smaller-p levels are compared with; ``spec_opt`` (default ``opt``)
     sets its limits, since the p = 2 Newton system of a planar graph grows ill-conditioned with n
-    and needs more CG steps than the levels after it.  With ``save`` set, U is
+    and needs more CG steps than the levels after it.  ``order`` "rcm" relabels the graph by the
+    library's reverse Cuthill-McKee order before the solve (the points are numbered at random, so
+    without it every neighbour gather misses the caches); "points" keeps the point order.  The
+    Riemannian HVP call is timed once per graph (``rhvp_ms``, p = 1.5).  With ``save`` set, U is
     written to ``save/U_r{r}_p{p}.npy`` after each level.  Returns a dict with one entry per level."""
     import os
     import time
 
     from . import gen
 
+    if order not in ("rcm", "points"):
+        raise ValueError(f"unknown order {order!r}")
     t0 = time.perf_counter()
     g = gen.delaunay(1 << r, seed=seed)
     t_graph = time.perf_counter() - t0
+    t_order = 0.0
+    if order == "rcm":
+        t0 = time.perf_counter()
+        g = gen.relabel(g, pspec.rcm_order(g.rowptr, g.col), "rcm")
+        t_order = time.perf_counter() - t0
     dg = pspec.Graph.from_host(g, "cuda", k_max=k)
     solver = Solver(dg, k, dtype, 1e-8)
     U = orthonormal_start(g.n, k, seed, dtype, "cuda")
     out = {"r": r, "n": g.n, "edges": g.nnz // 2, "k": k, "dtype": str(dtype).replace("torch.", ""),
-           "graph_seconds": round(t_graph, 2), "levels": []}
+           "order": order, "graph_seconds": round(t_graph, 2), "order_seconds": round(t_order, 2),
+           "rhvp_ms": _time_rhvp(dg, U, 1.5), "levels": []}
+    log(f"r={r} n={g.n} order={order} rhvp {out['rhvp_ms']:.3f} ms")
     for pl in p_levels(p, step):
         t1 = time.perf_counter()
-        U, info = rtr(solver, U, pl, spec_opt if (pl == 2.0 and spec_opt is not None) else opt)
+        def every10(it, F, gn, nt, pl=pl):
+            if it % 10 == 0:
+                log(f"r={r} p={pl:.2f}   outer {it:3d} F {F:.6e} |g| {gn:.2e} tcg {nt}")
+
+        U, info = rtr(solver, U, pl, spec_opt if (pl == 2.0 and spec_opt is not None) else opt, every10)
         torch.cuda.synchronize()
         t_solve = time.perf_counter() - t1
         Uh = U.double().cpu().numpy()
@@ -386,6 +417,20 @@ def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=
     out["rcut_spec"], out["rcut_pspec"] = spec, last
     out["rcut_gain_percent"] = 100.0 * (spec - last) / spec
     return out
+
+
+def _time_rhvp(dg: pspec.Graph, U: torch.Tensor, p: float, reps: int = 20) -> float:
+    """Milliseconds per Riemannian HVP call (pspec_rhvp) at U along V = U."""
+    RH, RG = torch.empty_like(U), torch.empty_like(U)
+    pspec.rhvp(dg, U, U, p, 1e-8, RH=RH, RG=RG)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        pspec.rhvp(dg, U, U, p, 1e-8, RH=RH, RG=RG)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
 
 
 def main(argv=None):
@@ -406,6 +451,8 @@ def main(argv=None):
     ap.add_argument("--spec-max-outer", type=int, default=100, help="outer limit at p = 2")
     ap.add_argument("--spec-tcg-max", type=int, default=300, help="tCG limit at p = 2")
     ap.add_argument("--save", default=None, help="directory for U after each p level (.npy)")
+    ap.add_argument("--order", choices=["rcm", "points"], default="rcm",
+                    help="node numbering: reverse Cuthill-McKee (default) or the random point order")
     a = ap.parse_args(argv)
     dtype = torch.float64 if a.dtype == "f64" else torch.float32
     rel = a.rel_tol if a.rel_tol is not None else (1e-6 if dtype == torch.float64 else 1e-4)
@@ -413,7 +460,7 @@ def main(argv=None):
     spec = TrustRegionOptions(max_outer=a.spec_max_outer, tcg_max=a.spec_tcg_max, rel_tol=rel)
     for r in a.r:
         res = delaunay_study(r, a.k, a.p, a.step, dtype, a.seed, opt, a.save,
-                             log=lambda s: print(s, flush=True), spec_opt=spec)
+                             log=lambda s: print(s, flush=True), spec_opt=spec, order=a.order)
         print(json.dumps(res), flush=True)
 
 

@@ -98,10 +98,10 @@ def delaunay(n: int, seed: int = SEED_GRAPH) -> Graph:
     return g
 
 
-def permute(g: Graph, seed: int) -> Graph:
-    """The same graph with node ids relabelled by a seeded random permutation (new id = perm[old]),
-    weights carried with their edges; columns ascend within each row of the result."""
-    perm = np.random.default_rng(seed).permutation(g.n).astype(np.int64)
+def relabel(g: Graph, perm: np.ndarray, name: str = "relabelled") -> Graph:
+    """The same graph with node ids relabelled (new id = perm[old]), weights carried with their
+    edges; columns ascend within each row of the result."""
+    perm = np.asarray(perm, dtype=np.int64)
     deg = np.diff(g.rowptr)
     rows = np.repeat(perm, deg)
     cols = perm[g.col.astype(np.int64)]
@@ -111,8 +111,19 @@ def permute(g: Graph, seed: int) -> Graph:
     rowptr = np.zeros(g.n + 1, dtype=np.int64)
     np.cumsum(np.bincount(new_rows, minlength=g.n), out=rowptr[1:])
     meta = dict(g.meta)
-    meta["permutation_seed"] = seed
-    return Graph(g.n, rowptr, cols[order].astype(np.int32), g.w[order], name=g.name + "-permuted", meta=meta)
+    if "points" in meta:
+        pts = np.empty_like(meta["points"])
+        pts[perm] = meta["points"]
+        meta["points"] = pts
+    return Graph(g.n, rowptr, cols[order].astype(np.int32), g.w[order], name=f"{g.name}-{name}", meta=meta)
+
+
+def permute(g: Graph, seed: int) -> Graph:
+    """The same graph with node ids relabelled by a seeded random permutation (new id = perm[old])."""
+    perm = np.random.default_rng(seed).permutation(g.n).astype(np.int64)
+    h = relabel(g, perm, "permuted")
+    h.meta["permutation_seed"] = seed
+    return h
 
 
 def csr_from_edges(n: int, i: np.ndarray, j: np.ndarray, weight_fn, name: str = "", meta=None) -> Graph:

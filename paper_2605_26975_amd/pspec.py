@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 # The in-tree build; PSPEC_LIBRARY may name another build of the same C ABI.
@@ -47,12 +48,14 @@ def lib() -> ctypes.CDLL:
         "pspec_objective": [vp, i32, i32, vp, i64, dbl, vp, vp, vp],
         "pspec_grad": [vp, i32, i32, vp, i64, dbl, vp, i64, vp, vp],
         "pspec_hvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp],
+        "pspec_hvp_sparse": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp],
         "pspec_rhvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp, sz, vp],
         "pspec_project": [i64, i32, i32, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, sz, vp],
         "pspec_retract": [i64, i32, i32, vp, i64, vp, i64, dbl, vp, i64, vp, vp, sz, vp],
         "pspec_dot": [i64, i32, i32, vp, i64, vp, i64, vp, vp, sz, vp],
         "pspec_axpby": [i64, i32, i32, dbl, vp, i64, dbl, vp, i64, vp],
         "pspec_kmeans_step": [i64, i32, i32, vp, i64, i32, vp, vp, vp, vp, vp, sz, vp],
+        "pspec_rcm_order": [i64, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -73,8 +76,9 @@ def exported_symbols() -> list[str]:
     return [
         "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info", "pspec_graph_set_timing_events",
         "pspec_objective", "pspec_grad",
-        "pspec_hvp", "pspec_rhvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
-        "pspec_axpby", "pspec_kmeans_workspace_bytes", "pspec_kmeans_step", "pspec_last_error",
+        "pspec_hvp", "pspec_hvp_sparse", "pspec_rhvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
+        "pspec_axpby", "pspec_kmeans_workspace_bytes", "pspec_kmeans_step", "pspec_rcm_order",
+        "pspec_last_error",
     ]
 
 
@@ -203,8 +207,10 @@ def grad(graph: Graph, U: torch.Tensor, p: float, G: torch.Tensor | None = None,
 
 
 def hvp(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float = 1e-8,
-        HV: torch.Tensor | None = None, G: torch.Tensor | None = None, F_col: torch.Tensor | None = None):
-    """Hessian of Eq. (1) at U applied to V, fused with the gradient: returns (HV, G, F_col)."""
+        HV: torch.Tensor | None = None, G: torch.Tensor | None = None, F_col: torch.Tensor | None = None,
+        sparse_only: bool = False):
+    """Hessian of Eq. (1) at U applied to V, fused with the gradient: returns (HV, G, F_col).
+    ``sparse_only`` drops the dense rank-2 part of the Hessian (pspec_hvp_sparse)."""
     ldu, ldv = _block(U, "U"), _block(V, "V")
     k = U.shape[1]
     if HV is None:
@@ -213,9 +219,9 @@ def hvp(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float = 1
         G = torch.empty(U.shape, dtype=U.dtype, device=U.device)
     if F_col is None:
         F_col = torch.empty(k, dtype=torch.float64, device=U.device)
-    _check(lib().pspec_hvp(graph.handle, _dtype_code(U), k, U.data_ptr(), ldu, V.data_ptr(), ldv, float(p), float(eps),
-                           HV.data_ptr(), _block(HV, "HV"), G.data_ptr(), _block(G, "G"), F_col.data_ptr(),
-                           _stream(U.device)))
+    fn = lib().pspec_hvp_sparse if sparse_only else lib().pspec_hvp
+    _check(fn(graph.handle, _dtype_code(U), k, U.data_ptr(), ldu, V.data_ptr(), ldv, float(p), float(eps),
+              HV.data_ptr(), _block(HV, "HV"), G.data_ptr(), _block(G, "G"), F_col.data_ptr(), _stream(U.device)))
     return HV, G, F_col
 
 
@@ -319,3 +325,14 @@ def kmeans_step(X: torch.Tensor, C: torch.Tensor, labels: torch.Tensor | None = 
     _check(lib().pspec_kmeans_step(n, d, _dtype_code(X), _ptr(X), ldx, c, _ptr(C), _ptr(labels), _ptr(dist),
                                    _ptr(stats), _ptr(ws), nbytes, _stream(X.device)))
     return labels, dist, stats
+
+
+def rcm_order(rowptr, col) -> np.ndarray:
+    """Reverse Cuthill-McKee relabelling of a symmetric host CSR graph: perm[old id] = new id
+    (computed by the library on the host; apply it with gen.relabel and to the rows of U)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    n = len(rowptr) - 1
+    perm = np.empty(max(n, 0), dtype=np.int64)
+    _check(lib().pspec_rcm_order(n, rowptr.ctypes.data, col.ctypes.data, perm.ctypes.data))
+    return perm

@@ -186,6 +186,42 @@ def pin_algorithm1_form(o):
             assert _rel(r, HVe[:, l]) < 1e-12
 
 
+def pin_hvp_sparse(o):
+    """Algorithm 1 read with sparse D[l], H[l]: the sparse Hessian part is (p/D) d/dt [Delta_p(u + t v)
+    - F phi_p(u + t v)] at t = 0 with D, F fixed, checked by central differences of the oracle's
+    p-Laplacian (pinned above) and of phi_p; assembled per column it is symmetric and zero off the
+    graph's pattern and diagonal; the exact operator minus it is -(p/D)(g a + phi b) with a = phi^T v,
+    b = g^T v (the rank-2 term)."""
+    rng = np.random.default_rng(21)
+    n, k = 12, 2
+    W = random_sym_weights(n, 0.4, rng)
+    rp, c, w = csr_from_dense(W)
+    U = spread_block(n, k, rng)
+    V = rng.standard_normal((n, k))
+    h = 1e-6
+    for p in (1.6, 1.3):
+        HVs = o.hvp_sparse(rp, c, w, U, V, p, 1e-12)
+        _, Fc, _, D = o.objective(rp, c, w, U, p)
+        phi = lambda X: np.sign(X) * np.abs(X) ** (p - 1)  # noqa: E731
+        Lp = o.plap(rp, c, w, U + h * V, p)
+        Lm = o.plap(rp, c, w, U - h * V, p)
+        fd = (p / D) * ((Lp - Lm) / (2 * h) - Fc * (phi(U + h * V) - phi(U - h * V)) / (2 * h))
+        assert np.max(np.abs(HVs - fd)) <= 1e-6 * np.max(np.abs(fd))
+        H = np.zeros((k, n, n))
+        for j in range(n):
+            E = np.zeros((n, k))
+            E[j, :] = 1.0
+            H[:, :, j] = o.hvp_sparse(rp, c, w, U, E, p, 1e-12).T
+        off = (W == 0) & ~np.eye(n, dtype=bool)
+        for l in range(k):
+            assert np.all(H[l][off] == 0.0)
+            assert np.max(np.abs(H[l] - H[l].T)) <= 1e-12 * np.max(np.abs(H[l]))
+        HV, G, _ = o.hvp(rp, c, w, U, V, p, 1e-12)
+        a = np.sum(phi(U) * V, axis=0)
+        b = np.sum(G * V, axis=0)
+        assert np.allclose(HV - HVs, -(p / D) * (G * a + phi(U) * b), rtol=1e-10, atol=1e-12)
+
+
 # --- p = 2: textbook Laplacian closed forms ----------------------------------------------------
 
 def pin_p2_closed_form(o):
@@ -395,6 +431,7 @@ ALL_PINS = [
     pin_projection,
     pin_retraction,
     pin_riemannian_hessian,
+    pin_hvp_sparse,
 ]
 
 

@@ -178,3 +178,28 @@ def test_rtr_continuation_decreases_f_at_each_level():
             print(f"{dtype} p={pl} outer {info.iterations} F {F[0]:.6f} -> {F[-1]:.6f}")
             assert np.all(np.diff(F) <= tol * F[:-1])
             assert F[-1] < F[0]
+
+
+def test_sparse_hessian_equals_exact_on_tangents_at_p2_only():
+    """At p = 2, phi(u) = u and tangent vectors X satisfy U^T X = 0, so the rank-2 part of the
+    Hessian, -(p/D)(g phi^T + phi g^T) X, lies in span(U) after a = phi^T x = 0 and is removed by
+    P_U: the Riemannian Hessians of the exact and sparse-only operators coincide.  Below p = 2 they
+    differ; the trust-region Newton with the sparse model still only accepts descent steps."""
+    n, k = 4096, 4
+    g = gen.delaunay(n, seed=7)
+    print(f"[case] sparse hessian delaunay n={n} k={k}", flush=True)
+    dg = gu.device_graph(g, k)
+    ex = driver.Solver(dg, k, torch.float64, 1e-8)
+    sp = driver.Solver(dg, k, torch.float64, 1e-8, hessian="sparse")
+    U = driver.orthonormal_start(n, k, 0, torch.float64, "cuda")
+    X, _ = pspec.project(U, torch.as_tensor(gen.block(n, k, gen.SEED_V)).double().cuda())
+    for p, same in ((2.0, True), (1.6, False)):
+        He = ex.hess(U, p, X, torch.empty_like(X)).cpu().numpy()
+        Hs = sp.hess(U, p, X, torch.empty_like(X)).cpu().numpy()
+        d = gu.rel(Hs, He)
+        print(f"p={p} rel diff {d:.2e}")
+        assert (d < 1e-10) if same else (d > 1e-6)
+    U2, _ = driver.rtr(ex, U, 2.0, driver.TrustRegionOptions(max_outer=20, rel_tol=1e-6))
+    _, info = driver.rtr(sp, U2, 1.6, driver.TrustRegionOptions(max_outer=20, rel_tol=1e-6))
+    F = np.asarray(info.F)
+    assert np.all(np.diff(F) <= 1e-13 * F[:-1]) and F[-1] < F[0]

@@ -143,3 +143,4 @@ def test_lloyd_hand_example():
     assert np.array_equal(lab, [0, 0, 1, 1])
     assert np.array_equal(C[:, 0], [0.5, 10.5])
     assert inertia == 1.0 and steps == 3
+

@@ -40,6 +40,11 @@ MUTANTS = {
                                   "sa += (long double)(phi_p(U[i * ldu + l], p) * V[i * ldv + (k - 1 - l)]);"),
     "hvp_transposed_gradient_index": ("double rank2 = g[i * k + l] * a[l]",
                                       "double rank2 = g[((n - 1 - i) * k) + l] * a[l]"),
+    "hvp_sparse_drop_diag": ("HV[i * k + l] = (p / D[l]) * (JL - Fl[l] * Jphi);", "HV[i * k + l] = (p / D[l]) * JL;"),
+    "hvp_sparse_diag_sign": ("HV[i * k + l] = (p / D[l]) * (JL - Fl[l] * Jphi);",
+                             "HV[i * k + l] = (p / D[l]) * (JL + Fl[l] * Jphi);"),
+    "hvp_sparse_psi_at_neighbour": ("double Jphi = (p - 1.0) * psi_eps(ui, p, eps) * vi;",
+                                    "double Jphi = (p - 1.0) * psi_eps(U[col[rowptr[i]] * ldu + l], p, eps) * vi;"),
 }
 
 
