@@ -35,6 +35,10 @@ METRIC = "p-Laplacian grad+HVP edge·col updates/s, FP32 vs FP64, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "edge_hvp_sbm8m_traffic.json")
+VALU_FILE = os.path.join(PROFILES, "edge_hvp_sbm8m_valu.json")
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP32_TRANS", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_SALU",
+                 "SQ_INSTS_LDS", "SQ_BUSY_CU_CYCLES")
+CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 EDGE_KERNEL = "edge_light<float, float, 16, 2>"  # the fused grad+HVP edge pass at k = 16
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
 WORKLOADS = {
@@ -76,6 +80,66 @@ def stored_traffic(workload: str, layout: str):
     if t.get("source_hash") != edge_source_hash() or t.get("workload") != workload or t.get("layout") != layout:
         return None
     return t.get("bytes_per_launch")
+
+
+def stored_valu(workload: str, layout: str, edge_ms: float):
+    """The VALU ceiling of the edge kernel from the committed counter summary (same source check as
+    the traffic): issue time of its VALU instructions (a wave64 instruction occupies a 16-lane SIMD
+    for 4 cycles; 4 SIMDs per CU; transcendentals counted at full rate, so a lower bound) against
+    the measured launch time, and the measured VALU busy fraction."""
+    try:
+        with open(VALU_FILE) as f:
+            v = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if v.get("source_hash") != edge_source_hash() or v.get("workload") != workload or v.get("layout") != layout:
+        return None
+    ceiling_ms = v["valu_issue_ms"]
+    return {"bound": "alu", "valu_issue_ms": ceiling_ms, "frac": ceiling_ms / edge_ms,
+            "valu_busy": v["valu_busy"], "valu_insts_per_edge_col": v["valu_insts_per_edge_col"]}
+
+
+def summarize_valu(pmc_dir: str, cmd: str, nnz: int, k: int) -> None:
+    """Write the VALU summary of the edge kernel from one rocprofv3 --pmc run of VALU_COUNTERS."""
+    import statistics
+
+    rows = _csv_rows(os.path.join(pmc_dir, "**", "*counter_collection.csv"))
+    is_edge = lambda nm: EDGE_KERNEL in nm.replace("pspec::(anonymous namespace)::", "")  # noqa: E731
+    med = {}
+    durs = {}
+    for r in rows:
+        if not is_edge(r["kernel_name"]):
+            continue
+        med.setdefault(r["counter_name"], []).append(float(r["counter_value"]))
+        durs[r["dispatch_id"]] = (float(r["end_timestamp"]) - float(r["start_timestamp"])) * 1e-6
+    med = {c: statistics.median(v) for c, v in med.items()}
+    dur_ms = statistics.median(durs.values())
+    valu = med["SQ_INSTS_VALU"]  # wave64 instructions, summed over the SIMDs of every SE
+    # issue cycles per CU: 4 cycles per wave64 VALU instruction on one of its 4 SIMDs
+    issue_ms = valu * 4 / 4 / CUS / CLOCK_HZ * 1e3
+    # rocprofv3's VALUBusy: SQ_ACTIVE_INST_VALU (quad-cycles summed over SIMDs) / CUs / cycles
+    busy = med["SQ_ACTIVE_INST_VALU"] / CUS / (CLOCK_HZ * dur_ms * 1e-3)
+    out = {
+        "workload": "sbm8m", "layout": "interleaved", "kernel": EDGE_KERNEL, "source_hash": edge_source_hash(),
+        "counters_per_dispatch": med, "dispatch_ms_under_counters": dur_ms,
+        "valu_insts_per_edge_col": valu * 64 / (nnz * k), "valu_issue_ms": issue_ms, "valu_busy": busy,
+        "command": cmd,
+    }
+    with open(VALU_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    md = ["# VALU work of the fused grad+HVP edge pass: SBM n=8,000,000, k=16, FP32", "",
+          "Counter run (from the repository root, one MI355X):", "", "```", cmd, "```", "",
+          "| quantity | value |", "|---|---|"]
+    md += [f"| {c} (per dispatch, median) | {v:.6g} |" for c, v in med.items()]
+    md += [f"| dispatch time under counters (ms) | {dur_ms:.4g} |",
+           f"| VALU lane-instructions per edge-col | {out['valu_insts_per_edge_col']:.4g} |",
+           f"| VALU issue time at {CUS} CUs x {CLOCK_HZ / 1e9:.1f} GHz, all at full rate (ms) | {issue_ms:.4g} |",
+           f"| VALU busy (rocprofv3 VALUBusy: SQ_ACTIVE_INST_VALU / CUs / cycles) | {busy:.3f} |", "",
+           "SQ_INSTS_VALU_FLOPS_FP32_TRANS reads 0.04 per edge-col where the kernel issues one v_log_f32 and "
+           "one v_exp_f32 per edge-col: that counter does not count them here, so the issue time takes "
+           "every VALU instruction at full rate (a lower bound; the two transcendentals run at quarter rate)."]
+    with open(os.path.join(PROFILES, "edge_hvp_sbm8m_valu.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
 
 
 class HipEvents:
@@ -231,10 +295,16 @@ def main() -> int:
                     help="skip the side measurements (per-call times, cold edge pass, streaming-read rate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
+    ap.add_argument("--summarize-valu", nargs=4, metavar=("PMC_DIR", "CMD", "NNZ", "K"),
+                    help="write the VALU counter summary of the edge kernel and exit")
     ap.add_argument("--summarize-profile", nargs=6, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_TRACE",
                                                             "CMD_FETCH", "CMD_WRITE"),
                     help="write the profiles/ summaries from rocprofv3 CSV output and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_valu:
+        summarize_valu(args.summarize_valu[0], args.summarize_valu[1], int(args.summarize_valu[2]),
+                       int(args.summarize_valu[3]))
+        return 0
     if args.summarize_profile:
         summarize_profile(*args.summarize_profile)
         return 0
@@ -457,6 +527,7 @@ def main() -> int:
             "kernel": "fused grad+HVP edge pass (light rows, heavy chunks, split-row combine)",
             "algorithmic_bytes_per_launch": alg_bytes,
             "launch_ms": edge_ms,
+            "valu": None if args.permute else stored_valu(args.workload, args.layout, edge_ms),
         },
         "edge_pass_value": nnz * k / (edge_ms * 1e-3),
         "measurements": None if more is None else dict(
