@@ -360,7 +360,8 @@ def cluster(graph: pspec.Graph, host_graph, k: int, p: float, dtype=torch.float3
 
 def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=torch.float64,
                    seed: int = 0, opt: TrustRegionOptions | None = None, save: str | None = None,
-                   log=print, spec_opt: TrustRegionOptions | None = None, order: str = "rcm") -> dict:
+                   log=print, spec_opt: TrustRegionOptions | None = None, order: str = "rcm",
+                   resume: str | None = None, time_rhvp: bool = True) -> dict:
     """The whole pipeline on a Delaunay graph of 2^r uniform random points (the stand-in for the
     paper's triangulation matrices, Section 3): trust-region Newton at each p level of the
     continuation, k-means on the rows of U and RCut after every level.  The p = 2 level is the
@@ -369,8 +370,11 @@ def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=
     and needs more CG steps than the levels after it.  ``order`` "rcm" relabels the graph by the
     library's reverse Cuthill-McKee order before the solve (the points are numbered at random, so
     without it every neighbour gather misses the caches); "points" keeps the point order.  The
-    Riemannian HVP call is timed once per graph (``rhvp_ms``, p = 1.5).  With ``save`` set, U is
-    written to ``save/U_r{r}_p{p}.npy`` after each level.  Returns a dict with one entry per level."""
+    Riemannian HVP call is timed once per graph (``rhvp_ms``, p = 1.5) unless ``time_rhvp`` is off.
+    With ``save`` set, U is written to ``save/U_r{r}_p{p:.2f}.npy`` after each level; with ``resume``
+    set to such a directory, the last level saved there is loaded (and clustered again) and the
+    continuation goes on from the next level; every kernel is deterministic, so a resumed run ends
+    with the same U as an uninterrupted one.  Returns a dict with one entry per level."""
     import os
     import time
 
@@ -391,9 +395,23 @@ def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=
     U = orthonormal_start(g.n, k, seed, dtype, "cuda")
     out = {"r": r, "n": g.n, "edges": g.nnz // 2, "k": k, "dtype": str(dtype).replace("torch.", ""),
            "order": order, "graph_seconds": round(t_graph, 2), "order_seconds": round(t_order, 2),
-           "rhvp_ms": _time_rhvp(dg, U, 1.5), "levels": []}
-    log(f"r={r} n={g.n} order={order} rhvp {out['rhvp_ms']:.3f} ms")
-    for pl in p_levels(p, step):
+           "rhvp_ms": _time_rhvp(dg, U, 1.5) if time_rhvp else None, "levels": []}
+    if time_rhvp:
+        log(f"r={r} n={g.n} order={order} rhvp {out['rhvp_ms']:.3f} ms")
+    checkpoint = lambda d, pl: os.path.join(d, f"U_r{r}_p{pl:.2f}.npy")  # noqa: E731
+    levels = p_levels(p, step)
+    start = 0
+    if resume:
+        saved = [i for i, pl in enumerate(levels) if os.path.exists(checkpoint(resume, pl))]
+        if saved:
+            i = saved[-1]
+            U = torch.as_tensor(np.load(checkpoint(resume, levels[i]))).to(dtype).to("cuda").contiguous()
+            labels, _, _ = kmeans_gpu(U, k, seed=seed)
+            out["levels"].append({"p": levels[i], "resumed": True, "F": solver.F(U, levels[i]),
+                                  "rcut": rcut(g.rowptr, g.col, g.w, labels)})
+            log(f"r={r} resumed after p={levels[i]:.2f} from {resume}")
+            start = i + 1
+    for pl in levels[start:]:
         t1 = time.perf_counter()
         def every10(it, F, gn, nt, pl=pl):
             if it % 10 == 0:
@@ -412,7 +430,7 @@ def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=
             f"|g|/|g0| {lev['grad_rel']:.1e} RCut {lev['rcut']:.5f} {t_solve:.1f}s")
         if save:
             os.makedirs(save, exist_ok=True)
-            np.save(os.path.join(save, f"U_r{r}_p{pl:.2f}.npy"), Uh)
+            np.save(checkpoint(save, pl), Uh)
     spec, last = out["levels"][0]["rcut"], out["levels"][-1]["rcut"]
     out["rcut_spec"], out["rcut_pspec"] = spec, last
     out["rcut_gain_percent"] = 100.0 * (spec - last) / spec
@@ -451,6 +469,7 @@ def main(argv=None):
     ap.add_argument("--spec-max-outer", type=int, default=100, help="outer limit at p = 2")
     ap.add_argument("--spec-tcg-max", type=int, default=300, help="tCG limit at p = 2")
     ap.add_argument("--save", default=None, help="directory for U after each p level (.npy)")
+    ap.add_argument("--resume", default=None, help="continue after the last level saved in this directory")
     ap.add_argument("--order", choices=["rcm", "points"], default="rcm",
                     help="node numbering: reverse Cuthill-McKee (default) or the random point order")
     a = ap.parse_args(argv)
@@ -460,7 +479,7 @@ def main(argv=None):
     spec = TrustRegionOptions(max_outer=a.spec_max_outer, tcg_max=a.spec_tcg_max, rel_tol=rel)
     for r in a.r:
         res = delaunay_study(r, a.k, a.p, a.step, dtype, a.seed, opt, a.save,
-                             log=lambda s: print(s, flush=True), spec_opt=spec, order=a.order)
+                             log=lambda s: print(s, flush=True), spec_opt=spec, order=a.order, resume=a.resume)
         print(json.dumps(res), flush=True)
 
 

@@ -203,3 +203,24 @@ def test_sparse_hessian_equals_exact_on_tangents_at_p2_only():
     _, info = driver.rtr(sp, U2, 1.6, driver.TrustRegionOptions(max_outer=20, rel_tol=1e-6))
     F = np.asarray(info.F)
     assert np.all(np.diff(F) <= 1e-13 * F[:-1]) and F[-1] < F[0]
+
+
+def test_delaunay_study_resumes_to_the_same_solution(tmp_path):
+    """A run stopped after p = 2 and resumed from its checkpoint ends with the same U, bit for bit,
+    as the uninterrupted run (every kernel and host step is deterministic)."""
+    import os
+
+    print("[case] delaunay study resume r=11", flush=True)
+    opt = driver.TrustRegionOptions(max_outer=15, rel_tol=1e-8)
+    full, part = str(tmp_path / "full"), str(tmp_path / "part")
+    a = driver.delaunay_study(11, k=4, p=1.6, step=0.2, opt=opt, save=full, log=print, time_rhvp=False)
+    os.makedirs(part)
+    name = "U_r11_p2.00.npy"
+    with open(os.path.join(full, name), "rb") as f, open(os.path.join(part, name), "wb") as g:
+        g.write(f.read())
+    b = driver.delaunay_study(11, k=4, p=1.6, step=0.2, opt=opt, save=part, resume=part, log=print,
+                              time_rhvp=False)
+    assert b["levels"][0].get("resumed") and [lv["p"] for lv in b["levels"]] == [2.0, 1.8, 1.6]
+    assert np.array_equal(np.load(os.path.join(full, "U_r11_p1.60.npy")),
+                          np.load(os.path.join(part, "U_r11_p1.60.npy")))
+    assert b["rcut_pspec"] == a["rcut_pspec"]
