@@ -6,9 +6,11 @@
 // centroid of smallest distance, so labels and distances are a plain function of the inputs (no
 // summation order to choose).  The per-cluster statistics (coordinate sums, count, distance sum) of
 // each 64-row wave batch are reduced across the wave (DPP exchanges within 16-lane rows, then the
-// four row sums; no LDS traffic) and accumulated, cluster j in lane j, in wave order; the four waves
-// of a workgroup are added in order into one partial per workgroup, and the kDenseBlocks partials
-// are added by the fixed two-level tree of the dense kernels.  The statistics are therefore bit-reproducible from run to run.  The work is one read of
+// four row sums; no LDS traffic) and accumulated, cluster j in lane j, in wave order; for at most
+// four clusters of at most 8 columns every lane instead keeps its own rows' statistics in registers
+// (in row order) and the wave reduces them once at the end.  The four waves of a workgroup are added
+// in order into one partial per workgroup, and the kDenseBlocks partials are added by the fixed
+// two-level tree of the dense kernels.  The statistics are therefore bit-reproducible from run to run.  The work is one read of
 // the block (plus the optional label and distance writes): HBM bound for the d and c of clustering U.
 #include "common.hpp"
 #include "dense.hpp"
@@ -58,7 +60,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
-template <typename T, int D, bool VEC>
+// Per-lane statistics are used when they fit in registers: at most kLocalC clusters of at most 8
+// columns (the clustering of U for small k).
+constexpr int kLocalC = 4;
+
+template <typename T, int D, bool VEC, bool LOCAL>
 __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const T *__restrict__ X, int64_t ldx,
                                                        int c, const double *__restrict__ C,
                                                        int32_t *__restrict__ labels, double *__restrict__ dist,
@@ -77,6 +83,13 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
     double acc[A];  // lane j < c: the statistics of cluster j over this wave's rows
 #pragma unroll
     for (int t = 0; t < A; ++t) acc[t] = 0.0;
+    // LOCAL: every lane's own statistics per cluster, reduced across the wave once at the end
+    constexpr int LC = LOCAL ? kLocalC : 1;
+    double la[LC][A];
+#pragma unroll
+    for (int j = 0; j < LC; ++j)
+#pragma unroll
+        for (int t = 0; t < A; ++t) la[j][t] = 0.0;
 
     for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
         const int64_t i = base + tid;
@@ -101,6 +114,17 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
             if (dist) dist[i] = best;
         }
         if (!valid) lab = -1;
+        if constexpr (LOCAL) {
+#pragma unroll
+            for (int j = 0; j < LC; ++j) {
+                const bool mine = lab == j;
+#pragma unroll
+                for (int t = 0; t < D; ++t) la[j][t] += mine ? x[t] : 0.0;
+                la[j][D] += mine ? 1.0 : 0.0;
+                la[j][D + 1] += mine ? best : 0.0;
+            }
+            continue;
+        }
         for (int j = 0; j < c; ++j) {
             const bool mine = lab == j;
             const uint64_t ball = __ballot(mine);
@@ -119,7 +143,15 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
         }
     }
 
-    if (lane < c) {
+    if constexpr (LOCAL) {
+#pragma unroll
+        for (int j = 0; j < LC; ++j)
+#pragma unroll
+            for (int t = 0; t < A; ++t) {
+                const double tot = wave_sum(la[j][t]);
+                if (lane == 0 && j < c) s_red[w][j][t] = tot;
+            }
+    } else if (lane < c) {
 #pragma unroll
         for (int t = 0; t < A; ++t) s_red[w][lane][t] = acc[t];
     }
@@ -140,10 +172,23 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
 template <typename T, int D>
 pspec_status kmeans_impl(int64_t n, int d, const T *X, int64_t ldx, int c, const double *C, int32_t *labels,
                          double *dist, double *stats, double *ws, hipStream_t s) {
-    if (rows_vectorisable<T, D>(d, {{X, ldx}}))
-        kmeans_partial<T, D, true><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+    const bool vec = rows_vectorisable<T, D>(d, {{X, ldx}});
+    if constexpr (D <= 8) {
+        if (c <= kLocalC) {
+            if (vec)
+                kmeans_partial<T, D, true, true><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+            else
+                kmeans_partial<T, D, false, true><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+            const int P = c * (d + 2);
+            sum_partials(ws, P, ws + (size_t)kDenseBlocks * P, stats, nullptr, s);
+            PSPEC_HIP(hipGetLastError());
+            return PSPEC_OK;
+        }
+    }
+    if (vec)
+        kmeans_partial<T, D, true, false><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
     else
-        kmeans_partial<T, D, false><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+        kmeans_partial<T, D, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
     const int P = c * (d + 2);
     sum_partials(ws, P, ws + (size_t)kDenseBlocks * P, stats, nullptr, s);
     PSPEC_HIP(hipGetLastError());
