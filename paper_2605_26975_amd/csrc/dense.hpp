@@ -114,6 +114,32 @@ __device__ __forceinline__ void pin_all(T (&x)[N]) {
     for (int i = 0; i < N; ++i) pin(x[i]);
 }
 
+// ---- wave reductions ---------------------------------------------------------------------------
+// One DPP lane exchange of a double (two 32-bit moves, VALU only).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum over the 64 lanes in a fixed order, the same value in every lane: within each 16-lane row,
+// partners exchanged by DPP (lanes i and i^1, then i^2, then i and 7-i within each half row, then i
+// and 15-i; each step adds two equal-sized partial sums, and since addition commutes both partners
+// hold the same result), then the four row sums read from lanes 0, 16, 32, 48.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 // ---- FP64 matrix cores ------------------------------------------------------------------------
 // v_mfma_f64_16x16x4f64 computes D = A B + C for A 16 x 4, B 4 x 16 and C, D 16 x 16.  Lane l
 // (l = 16 q + c, q < 4, c < 16) supplies A[c][q] and B[q][c] and holds D[4 i + q][c] in element i of
@@ -238,12 +264,92 @@ __device__ __forceinline__ void stage_matrix(const double *__restrict__ M, int k
     }
 }
 
-// Per-block partial of M = A^T B over a contiguous row range, on the FP64 matrix cores.
-// A = A1 + t A2 (rounded to T) when AXPY; B = A when SAME.
+// Gram rows of a workgroup for k <= 4 on the FP64 VALU, one lane per row (the matrix-core tile would
+// pad the rows to 16 columns and leave three quarters of its lanes idle; at k = 8 the 64 FP64
+// accumulators per lane would cost more occupancy than the padding does): lane l takes the rows r0 + l,
+// r0 + l + 256, ... in order (R at a time, clamped loads masked after the batch) and accumulates
+// acc[p][q] += a_p b_q by FMA.
+template <typename T, int K, bool AXPY, bool SAME, bool VEC>
+__device__ __forceinline__ void gram_rows_lane(int64_t r0, int64_t r1, int k, const T *__restrict__ A1, int64_t lda1,
+                                               const T *__restrict__ A2, int64_t lda2, double t,
+                                               const T *__restrict__ B, int64_t ldb, double (&acc)[K][K]) {
+    constexpr int R = (int)(K * sizeof(T)) >= 32 ? 1 : 32 / (int)(K * sizeof(T));  // rows per lane per batch
+    for (int64_t i0 = r0 + threadIdx.x; i0 < r1; i0 += (int64_t)R * kBlock) {
+        T a[R][K], a2[R][AXPY ? K : 1], b[R][SAME ? 1 : K];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int64_t i = clamp_index(i0 + (int64_t)u * kBlock, r1);
+            load_row<T, K, VEC>(A1 + i * lda1, k, a[u]);
+            if constexpr (AXPY) load_row<T, K, VEC>(A2 + i * lda2, k, a2[u]);
+            if constexpr (!SAME) load_row<T, K, VEC>(B + i * ldb, k, b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            pin_all(a[u]);
+            if constexpr (AXPY) pin_all(a2[u]);
+            if constexpr (!SAME) pin_all(b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const bool ok = i0 + (int64_t)u * kBlock < r1;
+            double x[K], y[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                T v = a[u][c];
+                if constexpr (AXPY) v = (T)((double)v + t * (double)a2[u][c]);
+                x[c] = ok ? (double)v : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                if constexpr (SAME) y[c] = x[c];
+                else y[c] = ok ? (double)b[u][c] : 0.0;
+            }
+#pragma unroll
+            for (int pa = 0; pa < K; ++pa)
+#pragma unroll
+                for (int qb = 0; qb < K; ++qb) acc[pa][qb] = fma(x[pa], y[qb], acc[pa][qb]);
+        }
+    }
+}
+
+// Per-block partial of M = A^T B over a contiguous row range: on the FP64 matrix cores for k > 4,
+// lane per row on the FP64 VALU up to 4.  A = A1 + t A2 (rounded to T) when AXPY; B = A when SAME.
 template <typename T, int K, bool AXPY, bool SAME>
 __global__ __launch_bounds__(kBlock) void gram_partial(int64_t n, int k, const T *__restrict__ A1, int64_t lda1,
                                                      const T *__restrict__ A2, int64_t lda2, double t,
                                                      const T *__restrict__ B, int64_t ldb, double *__restrict__ part) {
+    if constexpr (K <= 4) {
+        __shared__ double s_g[kBlock / 64][K * K];
+        int64_t r0, r1;
+        block_rows(n, r0, r1);
+        double acc[K][K];
+#pragma unroll
+        for (int pa = 0; pa < K; ++pa)
+#pragma unroll
+            for (int qb = 0; qb < K; ++qb) acc[pa][qb] = 0.0;
+        auto aligned = [](const void *ptr, int64_t ld) {
+            return ptr == nullptr || (((uintptr_t)ptr % 16) == 0 && ((size_t)ld * sizeof(T)) % 16 == 0);
+        };
+        const bool vec = k == K && aligned(A1, lda1) && (!AXPY || aligned(A2, lda2)) && (SAME || aligned(B, ldb));
+        if (vec)
+            gram_rows_lane<T, K, AXPY, SAME, true>(r0, r1, k, A1, lda1, A2, lda2, t, B, ldb, acc);
+        else
+            gram_rows_lane<T, K, AXPY, SAME, false>(r0, r1, k, A1, lda1, A2, lda2, t, B, ldb, acc);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int pa = 0; pa < K; ++pa)
+#pragma unroll
+            for (int qb = 0; qb < K; ++qb) {
+                const double v = wave_sum_f64(acc[pa][qb]);
+                if (lane == 0) s_g[w][pa * K + qb] = v;
+            }
+        __syncthreads();
+        for (int e = threadIdx.x; e < k * k; e += kBlock) {
+            const int idx = (e / k) * K + e % k;
+            part[(int64_t)blockIdx.x * k * k + e] = ((s_g[0][idx] + s_g[1][idx]) + s_g[2][idx]) + s_g[3][idx];
+        }
+        return;
+    }
     constexpr int CT = mf_tiles<K>();
     __shared__ double s_red[4][4][64];
     int64_t r0, r1;

@@ -35,31 +35,6 @@ __device__ __forceinline__ double sqdist(const double (&x)[D], const double *cj)
     return s;
 }
 
-// One DPP lane exchange of a double (two 32-bit moves, VALU only).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double lane_f64(double v, int lane) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
-                            __builtin_amdgcn_readlane(__double2loint(v), lane));
-}
-
-// Sum over the 64 lanes in a fixed order, the same value in every lane: within each 16-lane row,
-// partners exchanged by DPP (lanes i and i^1, then i^2, then i and 7-i within each half row, then i
-// and 15-i; each step adds two equal-sized partial sums, and since addition commutes both partners
-// hold the same result), then the four row sums read from lanes 0, 16, 32, 48.
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
-    v += dpp_f64<0x140>(v);  // row_mirror
-    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
-}
-
 // Per-lane statistics are used when they fit in registers: at most kLocalC clusters of at most 8
 // columns (the clustering of U for small k).
 constexpr int kLocalC = 4;
@@ -133,12 +108,12 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
 #pragma unroll
             for (int t = 0; t < D; ++t) {
                 if (t < d) {
-                    const double tot = wave_sum(mine ? x[t] : 0.0);
+                    const double tot = wave_sum_f64(mine ? x[t] : 0.0);
                     acc[t] += owner ? tot : 0.0;
                 }
             }
             acc[D] += owner ? (double)__popcll(ball) : 0.0;
-            const double tot = wave_sum(mine ? best : 0.0);
+            const double tot = wave_sum_f64(mine ? best : 0.0);
             acc[D + 1] += owner ? tot : 0.0;
         }
     }
@@ -148,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
         for (int j = 0; j < LC; ++j)
 #pragma unroll
             for (int t = 0; t < A; ++t) {
-                const double tot = wave_sum(la[j][t]);
+                const double tot = wave_sum_f64(la[j][t]);
                 if (lane == 0 && j < c) s_red[w][j][t] = tot;
             }
     } else if (lane < c) {
