@@ -35,7 +35,8 @@ enum Mode { OBJ = 0, GRAD = 1, HVP = 2 };
 //   sum s^(2j+1)/(2j+1) to j = 11 (|s| <= 0.172: truncation below 2^-60);  ln x = e ln 2 + ln m and
 //   t = q ln x as double-doubles (ln 2 split so that e ln2_hi is exact);  exp(t) = 2^n exp(r),
 //   n = rint(t / ln 2), |r| <= ln 2 / 2, exp(r) by its Taylor series to r^13 (truncation below
-//   2^-57).  A few units in the last place; q = 0 gives exactly 1; x = inf gives pow()'s limits.
+//   2^-57).  A few units in the last place; q = 0 gives exactly 1 (and is returned at once: p = 2 is
+//   the first level of every continuation); x = inf gives pow()'s limits.
 template <typename T>
 struct PowM2;
 template <>
@@ -53,6 +54,7 @@ struct PowM2<double> {
         constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;  // ln 2 to 42 bits: e * kLn2Hi is exact
         constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
         constexpr double kLog2e = 0x1.71547652b82fep0;
+        if (pm2 == 0.0) return 1.0;  // p = 2 (uniform branch): the routine below gives exactly 1 too
         const double x = fmax(ax, 0x1p-512);
         int e;
         double m = frexp(x, &e);  // [1/2, 1)
