@@ -206,9 +206,10 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     int64_t *tot = reinterpret_cast<int64_t *>(tmp + align256((size_t)nb * kCounters * sizeof(int64_t)));
     int *flag = reinterpret_cast<int *>(tot + kCounters);
 
+    // On a failure the first error is the one reported; the frees on that path are best effort.
     auto fail_hip = [&](const char *what, hipError_t e) {
         set_error("graph_create: %s: %s", what, hipGetErrorString(e));
-        hipFree(tmp);
+        (void)hipFree(tmp);
         return PSPEC_ERR_HIP;
     };
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
@@ -229,7 +230,7 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     int host_flag = 0;
     std::memcpy(&host_flag, &host_tot[kCounters], sizeof(int));
     if (host_flag != 0) {
-        hipFree(tmp);
+        (void)hipFree(tmp);
         set_error("graph_create: malformed CSR (%s%s)", (host_flag & 1) ? "row pointers" : "",
                   (host_flag & 2) ? " column indices out of range" : "");
         return PSPEC_ERR_ARG;
@@ -284,16 +285,21 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
                                                          g->splits);
     }
     if ((e = hipGetLastError()) != hipSuccess) {
-        hipFree(mem);
+        (void)hipFree(mem);
         delete g;
         return fail_hip("k_plan_emit", e);
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
-        hipFree(mem);
+        (void)hipFree(mem);
         delete g;
         return fail_hip("hipStreamSynchronize", e);
     }
-    hipFree(tmp);
+    if ((e = hipFree(tmp)) != hipSuccess) {
+        (void)hipFree(mem);
+        delete g;
+        set_error("graph_create: hipFree: %s", hipGetErrorString(e));
+        return PSPEC_ERR_HIP;
+    }
     *out = g;
     return PSPEC_OK;
 }
@@ -305,11 +311,12 @@ extern "C" pspec_status pspec_graph_destroy(pspec_graph g) {
     PSPEC_HIP(hipGetDevice(&cur));
     PSPEC_HIP(hipSetDevice(g->device));
     PSPEC_HIP(hipDeviceSynchronize());
-    hipError_t e = hipFree(g->mem);
-    hipSetDevice(cur);
+    const hipError_t e = hipFree(g->mem);
+    const hipError_t e2 = hipSetDevice(cur);  // restore the caller's device
     delete g;
-    if (e != hipSuccess) {
-        set_error("graph_destroy: hipFree: %s", hipGetErrorString(e));
+    if (e != hipSuccess || e2 != hipSuccess) {
+        set_error("graph_destroy: %s: %s", e != hipSuccess ? "hipFree" : "hipSetDevice",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
         return PSPEC_ERR_HIP;
     }
     return PSPEC_OK;
