@@ -4,14 +4,16 @@
 // One pass over the rows.  A thread owns a row: it computes the squared Euclidean distance to every
 // centroid as sum_t (x_t - c_t)^2 in t order with no fused multiply-add, and keeps the first
 // centroid of smallest distance, so labels and distances are a plain function of the inputs (no
-// summation order to choose).  The per-cluster statistics (coordinate sums, count, distance sum) of
-// each 64-row wave batch are reduced across the wave (DPP exchanges within 16-lane rows, then the
-// four row sums; no LDS traffic) and accumulated, cluster j in lane j, in wave order; for at most
-// four clusters of at most 8 columns every lane instead keeps its own rows' statistics in registers
-// (in row order) and the wave reduces them once at the end.  The four waves of a workgroup are added
-// in order into one partial per workgroup, and the kDenseBlocks partials are added by the fixed
-// two-level tree of the dense kernels.  The statistics are therefore bit-reproducible from run to run.  The work is one read of
-// the block (plus the optional label and distance writes): HBM bound for the d and c of clustering U.
+// summation order to choose).  The per-cluster statistics (coordinate sums, count, distance sum)
+// are gathered per wave in one of three ways (see Stat below): in each lane's registers (few
+// clusters and columns), as one-hot products on the FP64 matrix cores (up to 16 columns), or by a
+// DPP wave reduction per (cluster, column) pair and 64-row batch.  Every way adds in a fixed order;
+// the four waves of a workgroup are added in order into one partial per workgroup, and the
+// kDenseBlocks partials by the fixed two-level tree of the dense kernels, so the statistics are
+// bit-reproducible from run to run.  The work is one read of the block plus the optional label and
+// distance writes.
+#include <type_traits>
+
 #include "common.hpp"
 #include "dense.hpp"
 
@@ -35,15 +37,20 @@ __device__ __forceinline__ double sqdist(const double (&x)[D], const double *cj)
     return s;
 }
 
-// Per-lane statistics are used when they fit in registers: at most kLocalC clusters of at most 8
-// columns (the clustering of U for small k).
+// How the per-cluster statistics of a wave's rows are gathered:
+//   kStatLane  every lane keeps its own rows' statistics (at most kLocalC clusters of at most 8
+//              columns: the clustering of U for small k), one wave reduction at the end;
+//   kStatMfma  (at most 16 columns) per 64-row batch the wave stages its rows as [x | 1 | dist] in
+//              LDS and adds indicator(cluster)^T rows on the FP64 matrix cores, 16 steps of 4 rows;
+//   kStatWave  otherwise, a wave reduction per (cluster, column) pair and batch.
 constexpr int kLocalC = 4;
+enum Stat { kStatWave = 0, kStatLane = 1, kStatMfma = 2 };
 
-template <typename T, int D, bool VEC, bool LOCAL>
-__global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const T *__restrict__ X, int64_t ldx,
-                                                       int c, const double *__restrict__ C,
-                                                       int32_t *__restrict__ labels, double *__restrict__ dist,
-                                                       double *__restrict__ part) {
+template <typename T, int D, bool VEC, int STAT>
+__global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const T *__restrict__ X,
+                                                       int64_t ldx, int c, const double *__restrict__ C,
+                                                       int32_t *__restrict__ labels,
+                                                       double *__restrict__ dist, double *__restrict__ part) {
     constexpr int NW = kBlock / 64;
     constexpr int A = D + 2;  // accumulator slots: D coordinate sums, the count, the distance sum
     __shared__ double s_c[kKmMax][D];
@@ -58,8 +65,19 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
     double acc[A];  // lane j < c: the statistics of cluster j over this wave's rows
 #pragma unroll
     for (int t = 0; t < A; ++t) acc[t] = 0.0;
+    constexpr bool LOCAL = STAT == kStatLane, MF = STAT == kStatMfma;
     // LOCAL: every lane's own statistics per cluster, reduced across the wave once at the end
     constexpr int LC = LOCAL ? kLocalC : 1;
+    // MF: the wave's staged rows, their labels and the 16 x 16 tiles (clusters x columns)
+    constexpr int CTT = MF ? (A + 15) / 16 : 1;
+    constexpr int CTC = MF ? kKmMax / 16 : 1;
+    __shared__ double s_v[MF ? kBlock / 64 : 1][MF ? 64 : 1][A];
+    __shared__ int s_l[MF ? kBlock / 64 : 1][MF ? 64 : 1];
+    dbl4 mf[CTC][CTT];
+#pragma unroll
+    for (int ct = 0; ct < CTC; ++ct)
+#pragma unroll
+        for (int tt = 0; tt < CTT; ++tt) mf[ct][tt] = dbl4{0.0, 0.0, 0.0, 0.0};
     double la[LC][A];
 #pragma unroll
     for (int j = 0; j < LC; ++j)
@@ -100,6 +118,44 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
             }
             continue;
         }
+        if constexpr (MF) {
+            // stage this lane's row: columns < d the coordinates, d the count 1, d + 1 the distance
+            s_v[w][lane][D] = 0.0;
+            s_v[w][lane][D + 1] = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) s_v[w][lane][t] = x[t];
+            s_v[w][lane][d] = 1.0;
+            s_v[w][lane][d + 1] = best;
+            s_l[w][lane] = lab;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // lane (q, cc) supplies A[cc][q] = [label of row 4 st + q is 16 ct + cc] and
+            // B[q][cc] = column 16 tt + cc of row 4 st + q
+            const int q = lane >> 4, cc = lane & 15;
+            for (int st = 0; st < 16; ++st) {
+                const int row = 4 * st + q;
+                const int lj = s_l[w][row];
+                double bv[CTT];
+#pragma unroll
+                for (int tt = 0; tt < CTT; ++tt) {
+                    const int col = 16 * tt + cc;
+                    const double v = s_v[w][row][col < A ? col : A - 1];
+                    bv[tt] = col < A ? v : 0.0;
+                }
+#pragma unroll
+                for (int ct = 0; ct < CTC; ++ct) {
+                    if (16 * ct >= c) continue;  // wave-uniform
+                    const double av = lj == 16 * ct + cc ? 1.0 : 0.0;
+#pragma unroll
+                    for (int tt = 0; tt < CTT; ++tt) mf[ct][tt] = mfma_f64(av, bv[tt], mf[ct][tt]);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            continue;
+        }
         for (int j = 0; j < c; ++j) {
             const bool mine = lab == j;
             const uint64_t ball = __ballot(mine);
@@ -118,7 +174,20 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
         }
     }
 
-    if constexpr (LOCAL) {
+    if constexpr (MF) {
+        // element i of lane (q, cc) in tile (ct, tt): cluster 16 ct + 4 i + q, column 16 tt + cc
+        const int q = lane >> 4, cc = lane & 15;
+#pragma unroll
+        for (int ct = 0; ct < CTC; ++ct)
+#pragma unroll
+            for (int tt = 0; tt < CTT; ++tt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = 16 * ct + 4 * i + q, col = 16 * tt + cc;
+                    if (j < c && col < d + 2)
+                        s_red[w][j][col < d ? col : D + (col - d)] = mf[ct][tt][i];
+                }
+    } else if constexpr (LOCAL) {
 #pragma unroll
         for (int j = 0; j < LC; ++j)
 #pragma unroll
@@ -148,22 +217,19 @@ template <typename T, int D>
 pspec_status kmeans_impl(int64_t n, int d, const T *X, int64_t ldx, int c, const double *C, int32_t *labels,
                          double *dist, double *stats, double *ws, hipStream_t s) {
     const bool vec = rows_vectorisable<T, D>(d, {{X, ldx}});
-    if constexpr (D <= 8) {
-        if (c <= kLocalC) {
-            if (vec)
-                kmeans_partial<T, D, true, true><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
-            else
-                kmeans_partial<T, D, false, true><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
-            const int P = c * (d + 2);
-            sum_partials(ws, P, ws + (size_t)kDenseBlocks * P, stats, nullptr, s);
-            PSPEC_HIP(hipGetLastError());
-            return PSPEC_OK;
-        }
-    }
-    if (vec)
-        kmeans_partial<T, D, true, false><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+    auto launch = [&](auto stat) {
+        constexpr int ST = decltype(stat)::value;
+        if (vec)
+            kmeans_partial<T, D, true, ST><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+        else
+            kmeans_partial<T, D, false, ST><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+    };
+    if (D <= 8 && c <= kLocalC)
+        launch(std::integral_constant<int, D <= 8 ? kStatLane : kStatWave>{});
+    else if (D <= 16)
+        launch(std::integral_constant<int, D <= 16 ? kStatMfma : kStatWave>{});
     else
-        kmeans_partial<T, D, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
+        launch(std::integral_constant<int, kStatWave>{});
     const int P = c * (d + 2);
     sum_partials(ws, P, ws + (size_t)kDenseBlocks * P, stats, nullptr, s);
     PSPEC_HIP(hipGetLastError());
@@ -209,7 +275,8 @@ extern "C" pspec_status pspec_kmeans_step(int64_t n, int d, pspec_dtype dt, cons
     PSPEC_ARG(ws != nullptr, "kmeans_step: workspace is NULL");
     PSPEC_ARG(((uintptr_t)ws % 256) == 0, "kmeans_step: workspace must be 256-byte aligned");
     if (ws_bytes < kmeans_ws_doubles(c, d) * sizeof(double)) {
-        set_error("kmeans_step: workspace of %zu bytes < %zu needed", ws_bytes, kmeans_ws_doubles(c, d) * sizeof(double));
+        set_error("kmeans_step: workspace of %zu bytes < %zu needed", ws_bytes,
+                  kmeans_ws_doubles(c, d) * sizeof(double));
         return PSPEC_ERR_WORKSPACE;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
