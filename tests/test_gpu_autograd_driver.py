@@ -42,7 +42,7 @@ def test_autograd_gradient_vs_oracle_and_fd(grid128):
     (G32,) = torch.autograd.grad(F32, U32)
     _, Go, Fco = gu.oracle_hvp(g, U, V, p, eps)
     assert gu.rel(G32.double().cpu().numpy(), Go) < 1e-5
-    assert abs(float(F32) - Fco.sum()) / Fco.sum() < 1e-5
+    assert abs(float(F32.detach()) - Fco.sum()) / Fco.sum() < 1e-5
     # FP64 path: directional derivative against a central difference of F
     Vm, zeroed = _away_from_kinks(g, U, V)
     print(f"direction zeroed at {zeroed} of {V.size} entries near kinks")
