@@ -112,12 +112,14 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+# Workspaces of the dense calls, one per (device, stream, kind): the library requires that a
+# workspace is used by one call at a time, and calls on one stream run one after another.
 _ws_cache: dict = {}
 
 
 def _dense_ws(device, k: int) -> torch.Tensor:
     nbytes = int(lib().pspec_dense_workspace_bytes(k))
-    key = (str(device), k)
+    key = (str(device), _stream(device), k)
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
@@ -317,7 +319,7 @@ def kmeans_step(X: torch.Tensor, C: torch.Tensor, labels: torch.Tensor | None = 
         if t is not None and (not t.is_cuda or t.dtype != dt or t.numel() != size or not t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous {dt} device tensor of {size} elements")
     nbytes = int(lib().pspec_kmeans_workspace_bytes(c, d))
-    key = (str(X.device), "kmeans", c, d)
+    key = (str(X.device), _stream(X.device), "kmeans", c, d)
     ws = _ws_cache.get(key)
     if ws is None:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)

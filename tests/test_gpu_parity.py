@@ -346,3 +346,27 @@ def test_modes_agree_bitwise_with_heavy_rows(k):
     assert torch.equal(G, G2)
     for other in (Fc2, Fc3, Fc4):
         assert torch.equal(Fc, other)
+
+
+def test_dense_calls_on_two_streams_do_not_share_a_workspace():
+    """The binding keeps one dense workspace per stream: projections issued on two streams at once
+    give the same bits as on one stream."""
+    print("[case] project on two streams", flush=True)
+    n, k = 300_000, 8
+    U = torch.as_tensor(gen.block(n, k, gen.SEED_U)).cuda()
+    Z1 = torch.as_tensor(gen.block(n, k, gen.SEED_V)).cuda()
+    Z2 = torch.as_tensor(gen.block(n, k, 11)).cuda()
+    ref1 = pspec.project(U, Z1)[0].clone()
+    ref2 = pspec.project(U, Z2)[0].clone()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    outs = []
+    for _ in range(4):
+        with torch.cuda.stream(s1):
+            o1 = pspec.project(U, Z1)[0]
+        with torch.cuda.stream(s2):
+            o2 = pspec.project(U, Z2)[0]
+        outs.append((o1, o2))
+    torch.cuda.synchronize()
+    for o1, o2 in outs:
+        assert torch.equal(o1, ref1) and torch.equal(o2, ref2)
