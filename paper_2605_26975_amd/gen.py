@@ -118,6 +118,24 @@ def relabel(g: Graph, perm: np.ndarray, name: str = "relabelled") -> Graph:
     return Graph(g.n, rowptr, cols[order].astype(np.int32), g.w[order], name=f"{g.name}-{name}", meta=meta)
 
 
+def induced(g: Graph, keep: np.ndarray, name: str = "induced") -> tuple[Graph, np.ndarray]:
+    """The subgraph on the nodes with keep[i] true, renumbered in node order; returns it and the
+    original ids of its nodes.  Edges to dropped nodes are removed."""
+    keep = np.asarray(keep, dtype=bool)
+    ids = np.flatnonzero(keep).astype(np.int64)
+    new_id = np.full(g.n, -1, dtype=np.int64)
+    new_id[ids] = np.arange(len(ids))
+    rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    e = keep[rows] & keep[g.col]
+    r, c = new_id[rows[e]], new_id[g.col[e].astype(np.int64)]
+    rowptr = np.zeros(len(ids) + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=len(ids)), out=rowptr[1:])
+    meta = {k: v for k, v in g.meta.items() if k != "points"}
+    if "points" in g.meta:
+        meta["points"] = g.meta["points"][ids]
+    return Graph(len(ids), rowptr, c.astype(np.int32), g.w[e], name=f"{g.name}-{name}", meta=meta), ids
+
+
 def permute(g: Graph, seed: int) -> Graph:
     """The same graph with node ids relabelled by a seeded random permutation (new id = perm[old])."""
     perm = np.random.default_rng(seed).permutation(g.n).astype(np.int64)

@@ -144,3 +144,15 @@ def test_lloyd_hand_example():
     assert np.array_equal(C[:, 0], [0.5, 10.5])
     assert inertia == 1.0 and steps == 3
 
+
+
+def test_induced_subgraph():
+    """gen.induced keeps exactly the edges among kept nodes, renumbered in node order."""
+    g = gen.sbm_bernoulli(500, 4, 0.03, 0.004)
+    keep = np.random.default_rng(1).random(g.n) < 0.7
+    h, ids = gen.induced(g, keep)
+    assert np.array_equal(ids, np.flatnonzero(keep))
+    assert np.array_equal(h.to_dense(), g.to_dense()[np.ix_(ids, ids)])
+    for i in range(h.n):
+        c = h.col[h.rowptr[i]:h.rowptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
