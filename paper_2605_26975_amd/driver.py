@@ -444,7 +444,8 @@ def sbm_study(k: int = 16, p: float = 1.1, step: float = 0.2, dtype=torch.float3
     connected component, so its indicator column has F_p = 0 for every p and would be a trivial
     minimiser once p < 2), the rest is clustered by the trust-region continuation and k-means, and
     after every level the labels are scored against the planted blocks (matched accuracy over the
-    clustered vertices) and by RCut.  Isolated vertices get the label -1."""
+    clustered vertices) and by RCut, next to the RCut of the planted partition itself (the method
+    minimises RCut, which need not favour the planted blocks).  Isolated vertices get the label -1."""
     import time
 
     from . import gen
@@ -459,8 +460,9 @@ def sbm_study(k: int = 16, p: float = 1.1, step: float = 0.2, dtype=torch.float3
     solver = Solver(dg, k, dtype, 1e-8)
     U = orthonormal_start(g.n, k, seed, dtype, "cuda")
     out = {"n": g0.n, "isolated": int(g0.n - g.n), "k": k, "dtype": str(dtype).replace("torch.", ""),
-           "graph_seconds": round(t_graph, 2), "levels": []}
-    log(f"sbm8m: {g.n} of {g0.n} vertices have neighbours; graph {t_graph:.1f}s")
+           "graph_seconds": round(t_graph, 2), "rcut_planted": rcut(g.rowptr, g.col, g.w, truth), "levels": []}
+    log(f"sbm8m: {g.n} of {g0.n} vertices have neighbours; graph {t_graph:.1f}s; "
+        f"RCut of the planted blocks {out['rcut_planted']:.5f}")
     for pl in p_levels(p, step):
         t1 = time.perf_counter()
 
