@@ -102,3 +102,9 @@ def objective(U: torch.Tensor, graph: pspec.Graph, p: float, eps: float = 1e-8) 
 def gradient(U: torch.Tensor, graph: pspec.Graph, p: float, eps: float = 1e-8) -> torch.Tensor:
     """dF_p/dU, differentiable in U (its derivative is the Hessian-vector product kernel)."""
     return _Grad.apply(U, graph, p, eps)
+
+
+# Public names of the two Functions: PSpecF.apply(U, graph, p, eps) is F_p(U) as a 0-dim FP64 tensor,
+# PSpecGrad.apply(U, graph, p, eps) its gradient (backward and jvp: Hessian-vector products).
+PSpecF = _Objective
+PSpecGrad = _Grad
