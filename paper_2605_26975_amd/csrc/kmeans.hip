@@ -40,11 +40,12 @@ __device__ __forceinline__ double sqdist(const double (&x)[D], const double *cj)
 // How the per-cluster statistics of a wave's rows are gathered:
 //   kStatLane  every lane keeps its own rows' statistics (at most kLocalC clusters of at most 8
 //              columns: the clustering of U for small k), one wave reduction at the end;
-//   kStatMfma  (at most 16 columns) per 64-row batch the wave stages its rows as [x | 1 | dist] in
-//              LDS and adds indicator(cluster)^T rows on the FP64 matrix cores, 16 steps of 4 rows;
-//   kStatWave  otherwise, a wave reduction per (cluster, column) pair and batch.
+//   kStatMfma  otherwise: per 64-row batch the wave stages its rows as [x | 1 | dist] in LDS (all
+//              64 at once up to 16 columns, in two halves of 32 above) and adds
+//              indicator(cluster)^T rows on the FP64 matrix cores, one MFMA step per 4 rows.
+// The staging area shares its LDS with the per-wave results that are added at the end.
 constexpr int kLocalC = 4;
-enum Stat { kStatWave = 0, kStatLane = 1, kStatMfma = 2 };
+enum Stat { kStatLane = 1, kStatMfma = 2 };
 
 template <typename T, int D, bool VEC, int STAT>
 __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const T *__restrict__ X,
@@ -53,8 +54,13 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
                                                        double *__restrict__ dist, double *__restrict__ part) {
     constexpr int NW = kBlock / 64;
     constexpr int A = D + 2;  // accumulator slots: D coordinate sums, the count, the distance sum
+    constexpr bool LOCAL = STAT == kStatLane, MF = STAT == kStatMfma;
+    constexpr int RB = MF ? (D > 16 ? 32 : 64) : 1;  // rows of a batch staged at a time
+    constexpr int RED = NW * kKmMax * A, STG = MF ? NW * RB * A : 0;
     __shared__ double s_c[kKmMax][D];
-    __shared__ double s_red[NW][kKmMax][A];
+    __shared__ double s_big[RED > STG ? RED : STG];
+    auto s_red = reinterpret_cast<double (*)[kKmMax][A]>(s_big);  // [wave][cluster][slot], at the end
+    auto s_v = reinterpret_cast<double (*)[RB][A]>(s_big);         // [wave][row][column], MF batches
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int e = tid; e < kKmMax * D; e += kBlock) {
         const int j = e / D, t = e % D;
@@ -62,16 +68,11 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
     }
     __syncthreads();
 
-    double acc[A];  // lane j < c: the statistics of cluster j over this wave's rows
-#pragma unroll
-    for (int t = 0; t < A; ++t) acc[t] = 0.0;
-    constexpr bool LOCAL = STAT == kStatLane, MF = STAT == kStatMfma;
     // LOCAL: every lane's own statistics per cluster, reduced across the wave once at the end
     constexpr int LC = LOCAL ? kLocalC : 1;
     // MF: the wave's staged rows, their labels and the 16 x 16 tiles (clusters x columns)
     constexpr int CTT = MF ? (A + 15) / 16 : 1;
     constexpr int CTC = MF ? kKmMax / 16 : 1;
-    __shared__ double s_v[MF ? kBlock / 64 : 1][MF ? 64 : 1][A];
     __shared__ int s_l[MF ? kBlock / 64 : 1][MF ? 64 : 1];
     dbl4 mf[CTC][CTT];
 #pragma unroll
@@ -119,62 +120,51 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
             continue;
         }
         if constexpr (MF) {
-            // stage this lane's row: columns < d the coordinates, d the count 1, d + 1 the distance
-            s_v[w][lane][D] = 0.0;
-            s_v[w][lane][D + 1] = 0.0;
-#pragma unroll
-            for (int t = 0; t < D; ++t) s_v[w][lane][t] = x[t];
-            s_v[w][lane][d] = 1.0;
-            s_v[w][lane][d + 1] = best;
             s_l[w][lane] = lab;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // lane (q, cc) supplies A[cc][q] = [label of row 4 st + q is 16 ct + cc] and
-            // B[q][cc] = column 16 tt + cc of row 4 st + q
             const int q = lane >> 4, cc = lane & 15;
-            for (int st = 0; st < 16; ++st) {
-                const int row = 4 * st + q;
-                const int lj = s_l[w][row];
-                double bv[CTT];
+            for (int h = 0; h < 64 / RB; ++h) {
+                if (lane / RB == h) {
+                    // this lane's row: columns < d the coordinates, d the count 1, d + 1 the distance
+                    const int r = lane - h * RB;
+                    s_v[w][r][D] = 0.0;
+                    s_v[w][r][D + 1] = 0.0;
 #pragma unroll
-                for (int tt = 0; tt < CTT; ++tt) {
-                    const int col = 16 * tt + cc;
-                    const double v = s_v[w][row][col < A ? col : A - 1];
-                    bv[tt] = col < A ? v : 0.0;
+                    for (int t = 0; t < D; ++t) s_v[w][r][t] = x[t];
+                    s_v[w][r][d] = 1.0;
+                    s_v[w][r][d + 1] = best;
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // lane (q, cc) supplies A[cc][q] = [label of staged row 4 st + q is 16 ct + cc] and
+                // B[q][cc] = column 16 tt + cc of that row
+                for (int st = 0; st < RB / 4; ++st) {
+                    const int rr = 4 * st + q;
+                    const int lj = s_l[w][h * RB + rr];
+                    double bv[CTT];
 #pragma unroll
-                for (int ct = 0; ct < CTC; ++ct) {
-                    if (16 * ct >= c) continue;  // wave-uniform
-                    const double av = lj == 16 * ct + cc ? 1.0 : 0.0;
+                    for (int tt = 0; tt < CTT; ++tt) {
+                        const int col = 16 * tt + cc;
+                        const double v = s_v[w][rr][col < A ? col : A - 1];
+                        bv[tt] = col < A ? v : 0.0;
+                    }
 #pragma unroll
-                    for (int tt = 0; tt < CTT; ++tt) mf[ct][tt] = mfma_f64(av, bv[tt], mf[ct][tt]);
+                    for (int ct = 0; ct < CTC; ++ct) {
+                        if (16 * ct >= c) continue;  // wave-uniform
+                        const double av = lj == 16 * ct + cc ? 1.0 : 0.0;
+#pragma unroll
+                        for (int tt = 0; tt < CTT; ++tt) mf[ct][tt] = mfma_f64(av, bv[tt], mf[ct][tt]);
+                    }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            continue;
-        }
-        for (int j = 0; j < c; ++j) {
-            const bool mine = lab == j;
-            const uint64_t ball = __ballot(mine);
-            if (ball == 0) continue;  // wave-uniform: no row of this batch is in cluster j
-            const bool owner = lane == j;
-#pragma unroll
-            for (int t = 0; t < D; ++t) {
-                if (t < d) {
-                    const double tot = wave_sum_f64(mine ? x[t] : 0.0);
-                    acc[t] += owner ? tot : 0.0;
-                }
-            }
-            acc[D] += owner ? (double)__popcll(ball) : 0.0;
-            const double tot = wave_sum_f64(mine ? best : 0.0);
-            acc[D + 1] += owner ? tot : 0.0;
         }
     }
 
     if constexpr (MF) {
+        __syncthreads();  // every wave is done with its staging area, which s_red reuses
         // element i of lane (q, cc) in tile (ct, tt): cluster 16 ct + 4 i + q, column 16 tt + cc
         const int q = lane >> 4, cc = lane & 15;
 #pragma unroll
@@ -187,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
                     if (j < c && col < d + 2)
                         s_red[w][j][col < d ? col : D + (col - d)] = mf[ct][tt][i];
                 }
-    } else if constexpr (LOCAL) {
+    } else {
 #pragma unroll
         for (int j = 0; j < LC; ++j)
 #pragma unroll
@@ -195,9 +185,6 @@ __global__ __launch_bounds__(kBlock) void kmeans_partial(int64_t n, int d, const
                 const double tot = wave_sum_f64(la[j][t]);
                 if (lane == 0 && j < c) s_red[w][j][t] = tot;
             }
-    } else if (lane < c) {
-#pragma unroll
-        for (int t = 0; t < A; ++t) s_red[w][lane][t] = acc[t];
     }
     __syncthreads();
     // partial layout: part[j * (d + 2) + t], t < d the coordinate sums, t = d the count, t = d + 1
@@ -225,11 +212,9 @@ pspec_status kmeans_impl(int64_t n, int d, const T *X, int64_t ldx, int c, const
             kmeans_partial<T, D, false, ST><<<kDenseBlocks, kBlock, 0, s>>>(n, d, X, ldx, c, C, labels, dist, ws);
     };
     if (D <= 8 && c <= kLocalC)
-        launch(std::integral_constant<int, D <= 8 ? kStatLane : kStatWave>{});
-    else if (D <= 16)
-        launch(std::integral_constant<int, D <= 16 ? kStatMfma : kStatWave>{});
+        launch(std::integral_constant<int, D <= 8 ? kStatLane : kStatMfma>{});
     else
-        launch(std::integral_constant<int, kStatWave>{});
+        launch(std::integral_constant<int, kStatMfma>{});
     const int P = c * (d + 2);
     sum_partials(ws, P, ws + (size_t)kDenseBlocks * P, stats, nullptr, s);
     PSPEC_HIP(hipGetLastError());
