@@ -11,10 +11,12 @@
 //
 // Edge values are accumulated per row in the working precision T; every sum over rows is FP64:
 // each light workgroup (kTileRows rows) and each workgroup of the persistent heavy-chunk kernel
-// writes one FP64 partial row [kQ][k], and a two-stage reduction sums them in a fixed order.  The epilogue (finalize) turns
-// the raw rows L, J (stored in the G and HV outputs) into
+// writes one FP64 partial row [kQ][k], and a two-stage reduction sums them in a fixed order.  The
+// epilogue (finalize) turns the raw rows L, J (stored in the G and HV outputs) into
 //   G_i  = (p/D) (L_i - F phi_p(u_i))
-//   HV_i = (p/D) ((p-1) J_i - F (p-1) psi(u_i) v_i - G_i a - phi_p(u_i) b),  b = (p/D)(S - F a) = g^T v.
+//   HV_i = (p/D) ((p-1) J_i - F (p-1) psi(u_i) v_i - G_i a - phi_p(u_i) b),  b = (p/D)(S - F a) = g^T v;
+// the sparse-only Hessian (pspec_hvp_sparse) sets a = b = 0, dropping the rank-2 term.  The
+// Riemannian call (pspec_rhvp) fuses the epilogue with both projections for 16 <= k <= 32.
 #include <cmath>
 #include <type_traits>
 #include <utility>
