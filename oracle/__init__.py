@@ -25,6 +25,9 @@ spectral clustering with C++ GraphBLAS"):
                        nearest centroid by squared Euclidean distance (coordinates summed in order,
                        first minimum wins), per-cluster sums, sizes and distance sums.
 * ``lloyd``            Lloyd iterations from given centroids until the centroids stop changing.
+* ``error_scales``     not a result of the method: per-entry forward-error scales of G and HV (sums
+                       of the absolute values of their terms) that the parity tests bound the
+                       GPU's differences by.
 
 Every function's pins live in ``tests/test_oracle.py``.
 """
@@ -81,6 +84,9 @@ class Oracle:
         lib.oracle_hvp_sparse.argtypes = [_i64, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _i64, _f64p, _i64,
                                           _dbl, _dbl, _f64p]
         lib.oracle_hvp_sparse.restype = None
+        lib.oracle_error_scales.argtypes = [_i64, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _i64, _f64p, _i64,
+                                            _dbl, _dbl, _f64p, _f64p, opt]
+        lib.oracle_error_scales.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         self.lib = lib
@@ -167,6 +173,26 @@ class Oracle:
         HV = np.zeros_like(U)
         self.lib.oracle_hvp_sparse(n, rowptr, col, w, k, U, k, V, k, float(p), float(eps), HV)
         return HV
+
+
+    def error_scales(self, rowptr, col, w, U, V, p, eps, sparse=False):
+        """Returns (SG, SH): per-entry forward-error scales of the gradient and of the Hessian-vector
+        product (absolute-value sums of their terms, each power term weighted by its conditioning;
+        see oracle_error_scales); with ``sparse`` also SHs, the scale of the Hessian's sparse part.
+        For parity tolerances |x_gpu - x| <= tau * S, not a result of the method."""
+        rowptr, col, w = self._csr(rowptr, col, w)
+        n = len(rowptr) - 1
+        U = self._block(U, n)
+        V = self._block(V, n)
+        k = U.shape[1]
+        if V.shape[1] != k:
+            raise ValueError("U and V differ in k")
+        SG = np.zeros_like(U)
+        SH = np.zeros_like(U)
+        SHs = np.zeros_like(U) if sparse else None
+        self.lib.oracle_error_scales(n, rowptr, col, w, k, U, k, V, k, float(p), float(eps), SG, SH,
+                                     None if SHs is None else SHs.ctypes.data)
+        return (SG, SH, SHs) if sparse else (SG, SH)
 
 
 _default: Oracle | None = None

@@ -231,6 +231,87 @@ void oracle_hvp_sparse(int64_t n, const int64_t *rowptr, const int32_t *col, con
     free(Fl);
 }
 
+/*
+ * Forward-error scales of the gradient and the Hessian-vector product (for parity tolerances, not a
+ * result of the method).  Each entry of G and HV is a signed sum; its scale is the same sum taken
+ * over absolute values, every term weighted by the conditioning of the power that forms it: an
+ * absolute error d in log2|x| perturbs |x|^(p-2) = 2^((p-2) log2|x|) by the relative amount
+ * |p-2| ln2 d, and log2|x| is known to a relative accuracy, so a power term carries the weight
+ *   kappa(x) = 1 + |p - 2| |log2|x||  (phi_p, x != 0),   kappa_eps(x) = kappa(max(|x|, eps))  (psi).
+ * With x = u_i - u_j, phi = phi_p, psi = psi_eps, D = D_l, F = F_l, g = the gradient (column l):
+ *   SG_i = (p/D) [ sum_j w_ij |phi(x)| kappa(x) + F |phi(u_i)| kappa(u_i) ]
+ *   SH_i = (p/D) [ (p-1) sum_j w_ij psi(x) |v_i - v_j| kappa_eps(x)
+ *                  + F (p-1) psi(u_i) |v_i| kappa_eps(u_i) + SG_i |a| + |g_i| A + |phi(u_i)| B ]
+ * where a = phi^T v, A = sum_i |phi(u_i) v_i| kappa(u_i) and B = sum_i SG_i |v_i| bound the errors
+ * of the two inner products of the rank-2 part.  SHs (may be NULL) receives the scale of the sparse
+ * part alone (the first line of SH_i: the Hessian without its rank-2 term).  An evaluation whose every elementary operation
+ * has a relative error below r in any order agrees with the exact value to (c + m) r times the
+ * scale, m being the longest sequential sum; SG_i >= |g_i| and SH_i >= |(Hv)_i| always.
+ */
+static double kappa(double x, double q) { return 1.0 + q * fabs(log2(fabs(x))); }
+static double kappa_eps(double x, double q, double eps) { return 1.0 + q * fabs(log2(fabs(x) > eps ? fabs(x) : eps)); }
+
+void oracle_error_scales(int64_t n, const int64_t *rowptr, const int32_t *col, const double *w,
+                         int k, const double *U, int64_t ldu, const double *V, int64_t ldv,
+                         double p, double eps, double *SG, double *SH, double *SHs)
+{
+    double *g = (double *)malloc(sizeof(double) * (size_t)n * (size_t)k);
+    double *D = (double *)malloc(sizeof(double) * (size_t)k);
+    double *Fl = (double *)malloc(sizeof(double) * (size_t)k);
+    double *a = (double *)malloc(sizeof(double) * (size_t)k);
+    double *A = (double *)malloc(sizeof(double) * (size_t)k);
+    double *B = (double *)malloc(sizeof(double) * (size_t)k);
+    const double q = fabs(p - 2.0);
+    oracle_objective(n, rowptr, col, w, k, U, ldu, p, NULL, D, Fl, NULL);
+    oracle_grad(n, rowptr, col, w, k, U, ldu, p, g, NULL);
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 512)
+    for (i = 0; i < n; ++i) {
+        for (int l = 0; l < k; ++l) {
+            double ui = U[i * ldu + l], vi = V[i * ldv + l];
+            long double sg = 0.0L, sh = 0.0L;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                int64_t j = col[e];
+                double x = ui - U[j * ldu + l];
+                if (x != 0.0) sg += (long double)(w[e] * fabs(phi_p(x, p)) * kappa(x, q));
+                sh += (long double)(w[e] * psi_eps(x, p, eps) * fabs(vi - V[j * ldv + l]) * kappa_eps(x, q, eps));
+            }
+            double phi_i = ui != 0.0 ? fabs(phi_p(ui, p)) * kappa(ui, q) : 0.0;
+            SG[i * k + l] = (p / D[l]) * ((double)sg + Fl[l] * phi_i);
+            SH[i * k + l] = (double)sh * (p - 1.0) + Fl[l] * (p - 1.0) * psi_eps(ui, p, eps) * fabs(vi) *
+                                                         kappa_eps(ui, q, eps);
+        }
+    }
+    for (int l = 0; l < k; ++l) {
+        long double sa = 0.0L, sA = 0.0L, sB = 0.0L;
+        for (i = 0; i < n; ++i) {
+            double ui = U[i * ldu + l], vi = V[i * ldv + l];
+            sa += (long double)(phi_p(ui, p) * vi);
+            if (ui != 0.0) sA += (long double)(fabs(phi_p(ui, p) * vi) * kappa(ui, q));
+            sB += (long double)(SG[i * k + l] * fabs(vi));
+        }
+        a[l] = (double)sa;
+        A[l] = (double)sA;
+        B[l] = (double)sB;
+    }
+    if (SHs)
+        for (int64_t q2 = 0; q2 < n * (int64_t)k; ++q2) SHs[q2] = (p / D[q2 % k]) * SH[q2];
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        for (int l = 0; l < k; ++l) {
+            double ui = U[i * ldu + l];
+            double rank2 = SG[i * k + l] * fabs(a[l]) + fabs(g[i * k + l]) * A[l] + fabs(phi_p(ui, p)) * B[l];
+            SH[i * k + l] = (p / D[l]) * (SH[i * k + l] + rank2);
+        }
+    }
+    free(g);
+    free(D);
+    free(Fl);
+    free(a);
+    free(A);
+    free(B);
+}
+
 /* Number of OpenMP threads a parallel region of this library uses (1 without OpenMP). */
 int oracle_num_threads(void)
 {

@@ -77,12 +77,22 @@ def test_rhvp_vs_oracle(dtype):
     HVo, Go, Fco = gu.oracle_hvp(g, Ur, Vr, p, eps)
     RGo, MGo = orc.project(Ur, Go)
     RHo = orc.riemannian_hessian(Ur, Go, HVo, Vr)
-    tol_g, tol_h = (1e-5, 1e-4) if dtype == torch.float32 else (1e-11, 1e-11)
+    # element-wise scales: G's and HV's errors carried through the projections,
+    # RG = G - U (U^T G), RH = HV - U (U^T HV) - V (U^T G)
+    SG, SH = gu.oracle_scales(g, Ur, Vr, p, eps)
+    aU, aV = np.abs(Ur), np.abs(Vr)
+    S_RG = SG + aU @ (aU.T @ SG)
+    S_RH = SH + aU @ (aU.T @ SH) + aV @ (aU.T @ SG)
+    t = gu.TOLS[dtype]
+    RGh, RHh = RG.double().cpu().numpy(), RH.double().cpu().numpy()
     e = dict(F=float(np.max(np.abs(Fc.cpu().numpy() - Fco) / np.abs(Fco))),
-             MG=gu.rel(MG.cpu().numpy(), MGo), RG=gu.rel(RG.double().cpu().numpy(), RGo),
-             RH=gu.rel(RH.double().cpu().numpy(), RHo))
+             MG=gu.ew(MG.cpu().numpy(), MGo, aU.T @ SG), RG=gu.rel(RGh, RGo), RH=gu.rel(RHh, RHo),
+             RG_colmax=gu.colmax(RGh, RGo), RH_colmax=gu.colmax(RHh, RHo),
+             RG_ew=gu.ew(RGh, RGo, S_RG), RH_ew=gu.ew(RHh, RHo, S_RH))
     print(e)
-    assert e["F"] < tol_g and e["MG"] < tol_g and e["RG"] < tol_g and e["RH"] < tol_h, e
+    assert e["F"] <= t["F"] and e["MG"] <= t["tau"], e
+    assert max(e["RG"], e["RH"], e["RG_colmax"], e["RH_colmax"]) <= t["norm"], e
+    assert e["RG_ew"] <= t["tau"] and e["RH_ew"] <= t["tau"], e
     # RG is tangent at U, and so is RH (for tangent V the correction term keeps it there)
     Ut = torch.as_tensor(Ur).cuda()
     assert float((Ut.T @ RG.double()).abs().max()) < (1e-5 if dtype == torch.float32 else 1e-12)

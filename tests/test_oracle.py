@@ -156,3 +156,67 @@ def test_induced_subgraph():
     for i in range(h.n):
         c = h.col[h.rowptr[i]:h.rowptr[i + 1]]
         assert np.all(np.diff(c) > 0)
+
+
+def _dense_scales(W, U, V, p, eps):
+    """The error scales of oracle_error_scales from their definition, over a dense weight matrix."""
+    n, k = U.shape
+    q = abs(p - 2.0)
+    phi = lambda x: np.sign(x) * np.abs(x) ** (p - 1.0)  # noqa: E731
+    psi = lambda x: np.maximum(np.abs(x), eps) ** (p - 2.0)  # noqa: E731
+    kap = lambda x: 1.0 + q * np.abs(np.log2(np.abs(x)))  # noqa: E731
+    kape = lambda x: 1.0 + q * np.abs(np.log2(np.maximum(np.abs(x), eps)))  # noqa: E731
+    SG = np.zeros((n, k))
+    SH = np.zeros((n, k))
+    for l in range(k):
+        u, v = U[:, l], V[:, l]
+        D = np.sum(np.abs(u) ** p)
+        F = 0.5 * sum(W[i, j] * abs(u[i] - u[j]) ** p for i in range(n) for j in range(n)) / D
+        L = np.array([sum(W[i, j] * phi(u[i] - u[j]) for j in range(n)) for i in range(n)])
+        g = (p / D) * (L - F * phi(u))
+        for i in range(n):
+            s = sum(W[i, j] * abs(phi(u[i] - u[j])) * kap(u[i] - u[j]) for j in range(n) if u[i] != u[j])
+            SG[i, l] = (p / D) * (s + F * abs(phi(u[i])) * (kap(u[i]) if u[i] != 0 else 0.0))
+        a = float(np.dot(phi(u), v))
+        A = sum(abs(phi(u[i]) * v[i]) * kap(u[i]) for i in range(n) if u[i] != 0)
+        B = float(np.sum(SG[:, l] * np.abs(v)))
+        for i in range(n):
+            s = sum(W[i, j] * psi(u[i] - u[j]) * abs(v[i] - v[j]) * kape(u[i] - u[j]) for j in range(n))
+            SH[i, l] = (p / D) * ((p - 1.0) * s + F * (p - 1.0) * psi(u[i]) * abs(v[i]) * kape(u[i])
+                                  + SG[i, l] * abs(a) + abs(g[i]) * A + abs(phi(u[i])) * B)
+    return SG, SH
+
+
+@pytest.mark.parametrize("p", [2.0, 1.3, 1.05])
+def test_error_scales(oracle_lib, p):
+    """The parity tolerances' per-entry scales: equal to their definition on a dense 9-node graph
+    (with an exact tie, a zero entry and a sub-eps difference); never below |G| or |HV|; at p = 2
+    they reduce to (2/D)(sum_j w |u_i - u_j| + F |u_i|) for the gradient."""
+    rng = np.random.default_rng(11)
+    W = pins.random_sym_weights(9, 0.6, rng)
+    U = rng.normal(size=(9, 3))
+    U[2, 0] = U[5, 0]            # exact tie on an edge or not: x = 0
+    U[4, 1] = 0.0                # phi_p(0) = 0
+    U[7, 2] = U[1, 2] + 3e-9     # |x| below eps
+    V = rng.normal(size=(9, 3))
+    rowptr, col, w = pins.csr_from_dense(W)
+    SG, SH = oracle_lib.error_scales(rowptr, col, w, U, V, p, 1e-8)
+    SGd, SHd = _dense_scales(W, U, V, p, 1e-8)
+    assert np.allclose(SG, SGd, rtol=1e-12, atol=0) and np.allclose(SH, SHd, rtol=1e-12, atol=0)
+    HV, G, _ = oracle_lib.hvp(rowptr, col, w, U, V, p, 1e-8)
+    assert np.all(SG >= np.abs(G)) and np.all(SH >= np.abs(HV))
+    if p == 2.0:
+        D = np.sum(U ** 2, axis=0)
+        F = np.array([0.5 * np.sum(W * (U[:, l][:, None] - U[:, l][None, :]) ** 2) / D[l] for l in range(3)])
+        absx = np.abs(U[:, None, :] - U[None, :, :])
+        ref = (2.0 / D) * (np.einsum("ij,ijl->il", W, absx) + F * np.abs(U))
+        assert np.allclose(SG, ref, rtol=1e-12, atol=0)
+    # larger graph: the bounds hold everywhere
+    g = gen.sbm_bernoulli(300, 3, 0.1, 0.01, seed=3)
+    U = gen.block(g.n, 4, gen.SEED_U).astype(np.float64)
+    V = gen.block(g.n, 4, gen.SEED_V).astype(np.float64)
+    SG, SH, SHs = oracle_lib.error_scales(g.rowptr, g.col, g.w, U, V, p, 1e-8, sparse=True)
+    HV, G, _ = oracle_lib.hvp(g.rowptr, g.col, g.w, U, V, p, 1e-8)
+    HVs = oracle_lib.hvp_sparse(g.rowptr, g.col, g.w, U, V, p, 1e-8)
+    assert np.all(SG >= np.abs(G)) and np.all(SH >= np.abs(HV))
+    assert np.all(SHs >= np.abs(HVs)) and np.all(SHs <= SH)
