@@ -253,10 +253,13 @@ def summarize_profile(trace_dir: str, fetch_dir: str, write_dir: str, cmd_trace:
 
 
 def cpu_baseline(g, U_h, V_h, k: int, p: float, eps: float, workload: str):
-    """Time the FP64 oracle (as it stands) for one grad+HVP call on the benchmarked graph and block."""
+    """Time the FP64 oracle (as it stands) for one grad+HVP call on the benchmarked graph and block,
+    on every host core; and single-threaded on a bounded sample of the same workload (the rows of the
+    first SBM block and the edges among them, the induced subgraph: ~1/16 of the graph)."""
     import numpy as np
 
     import oracle
+    from paper_2605_26975_amd import gen
 
     o = oracle.default()
     U = U_h.astype(np.float64)
@@ -265,13 +268,30 @@ def cpu_baseline(g, U_h, V_h, k: int, p: float, eps: float, workload: str):
     t0 = time.perf_counter()
     o.hvp(g.rowptr, g.col, w, U, V, p, eps)
     dt = time.perf_counter() - t0
+    cores = o.num_threads()
+    # single thread on the first block (block-contiguous ids: rows [0, n / 16))
+    keep = np.zeros(g.n, dtype=bool)
+    keep[: g.n // 16] = True
+    sub, old = gen.induced(g, keep)
+    o.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        o.hvp(sub.rowptr, sub.col, sub.w.astype(np.float64), U[old], V[old], p, eps)
+        dt1 = time.perf_counter() - t1
+    finally:
+        o.set_num_threads(cores)
     return {
         "value": g.nnz * k / dt,
         "unit": "edge*col updates/s",
-        "cores": o.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"one FP64 oracle grad+HVP call on the full {workload} graph and block (n={g.n}, nnz={g.nnz}, "
-                  f"k={k}, p={p}): {dt:.2f} s",
+                  f"k={k}, p={p}): {dt:.2f} s on {cores} threads",
+        "single_thread": {
+            "value": sub.nnz * k / dt1, "unit": "edge*col updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 oracle grad+HVP call, 1 thread, on the subgraph induced by the first block "
+                      f"(n={sub.n}, nnz={sub.nnz}, k={k}, p={p}): {dt1:.2f} s",
+        },
     }
 
 
@@ -430,6 +450,17 @@ def main() -> int:
             b.record()
             torch.cuda.synchronize()
             ms[name] = a.elapsed_time(b) / reps
+        # the gather floor: the same edge pass with its arithmetic replaced by a sum of the gathered
+        # values (same kernels, grid, loads and stores), timed by the same events
+        evs = HipEvents(reps)
+        pspec.hvp_gather_floor(dg, U, V, HV=HV, G=G)
+        for i in range(reps):
+            dg.set_timing_events_raw(*evs.pairs[i])
+            pspec.hvp_gather_floor(dg, U, V, HV=HV, G=G)
+            dg.set_timing_events_raw(None, None)
+        torch.cuda.synchronize()
+        floor = [evs.elapsed_ms(i) for i in range(reps)]
+        evs.close()
         # edge pass with a cold Infinity Cache: 512 MiB written before every run
         flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         evs = HipEvents(reps)
@@ -460,6 +491,7 @@ def main() -> int:
             "call_ms": ms,
             "hvp_call_value": nnz * k / (ms["hvp"] * 1e-3),
             "edge_pass_cold_ms": float(np.mean(cold)),
+            "gather_floor_ms": float(np.mean(floor)),
             "kmeans_step_GBps": (n * k * U.element_size() + 4 * n) / (ms["kmeans_step"] * 1e-3) / 1e9,
             "read_stream_GBps": read_gbs,
         }
@@ -531,7 +563,8 @@ def main() -> int:
         },
         "edge_pass_value": nnz * k / (edge_ms * 1e-3),
         "measurements": None if more is None else dict(
-            more, edge_frac_of_read_stream=achieved / more["read_stream_GBps"]),
+            more, edge_frac_of_read_stream=achieved / more["read_stream_GBps"],
+            edge_frac_of_gather_floor=more["gather_floor_ms"] / edge_ms),
         "fp64": fp64,
         "speedup_fp32_over_fp64": (fp64["ms_per_step"] / t32) if fp64 else None,
         "finite": ok32,

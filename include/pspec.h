@@ -25,13 +25,20 @@
  *          each neighbour gather a single contiguous 2k-value row.
  * Memory.  Every array argument is a DEVICE pointer owned by the caller, unless stated otherwise.
  *          Scalar results (F, F_col, M) are FP64 device arrays, so the caller decides when to copy.
+ *          The library never allocates device memory: every buffer beyond the inputs and outputs
+ *          is a workspace the caller passes in (sizes from the *_workspace_bytes functions).
  * Streams. Every call enqueues its kernels on `stream` and returns without synchronising, except
  *          pspec_graph_create (which synchronises `stream` once, see there).  `stream` may be NULL
  *          (the null stream).  A graph handle holds the scratch of its calls: at most one call per
  *          handle may be in flight at a time.
- * Types.   dt = PSPEC_F32: U/V/G/HV are float; edge arithmetic in FP32 (|x|^(p-2) via the hardware
- *          exp2/log2), every reduction (numerators, p-norms, dot products, Gram matrices) in FP64.
- *          dt = PSPEC_F64: everything double, |x|^(p-2) via the device-library pow().
+ * Types.   dt = PSPEC_F32: U/V/G/HV are float; edge arithmetic in FP32 (|x|^(p-2) as
+ *          exp2((p-2) log2 max(|x|, 2^-64)) with the hardware exp2/log2), every reduction (numerators,
+ *          p-norms, dot products, Gram matrices) in FP64.
+ *          dt = PSPEC_F64: everything double; |x|^(p-2) by the library's own exp((p-2) ln x) (ln x
+ *          from an atanh series in double-double, exp by a Taylor series after reduction by ln 2;
+ *          within a few units in the last place of the C library's pow), with x clamped to
+ *          [2^-512, inf) (so only 0 < |x| < 2^-512 is affected; exact zeros stay exact) and exactly 1
+ *          at p = 2.
  * Errors.  Argument errors are found on the host before anything is launched and return
  *          PSPEC_ERR_ARG (PSPEC_ERR_UNSUPPORTED for valid but unsupported requests); a failed HIP
  *          call returns PSPEC_ERR_HIP.  pspec_last_error() describes the last failure of the
@@ -63,7 +70,8 @@ typedef enum {
 
 typedef enum { PSPEC_F32 = 0, PSPEC_F64 = 1 } pspec_dtype;
 
-/* Opaque handle: a CSR graph (borrowed) plus its row schedule and scratch (owned). */
+/* Opaque handle (a small host object): a CSR graph and the row schedule and scratch built in the
+ * caller's workspace, both borrowed. */
 typedef struct pspec_graph_s *pspec_graph;
 
 /* HIP's hipStream_t and hipEvent_t, declared opaquely so this header needs no HIP headers. */
@@ -74,32 +82,49 @@ typedef struct ihipEvent_t *pspec_event;
 #define PSPEC_K_MAX 64
 
 /*
- * pspec_graph_create -- build the row schedule of a graph (degree binning).
+ * pspec_graph_workspace_bytes -- device workspace a graph handle needs (the state behind the
+ * EucGrad / EucHessianEta callbacks of Section 2: row schedule, FP64 partial sums, per-column
+ * scalars, partial rows of long rows).  A bound from the sizes alone, valid for every CSR with n
+ * nodes and nnz stored entries: with h = min(n, nnz / (PSPEC_LIGHT_MAX + 1)) possible heavy rows
+ * and s = min(n, nnz / (PSPEC_CHUNK + 1)) possible split rows it is about
+ *   24 (nnz / PSPEC_CHUNK + h) + 16 s + 16 k_max (nnz / PSPEC_CHUNK + s)
+ *   + 32 k_max (n / 256 + 2048) + 8240 k_max + 32 n / 256        bytes
+ * (SBM n = 8M, nnz = 96M, k_max = 16: ~190 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32: ~380 MB).
+ * Returns 0 for arguments pspec_graph_create would reject (n < 1, nnz < 0, k_max outside
+ * 1..PSPEC_K_MAX, n >= 2^31 - 1).
+ */
+size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max);
+
+/*
+ * pspec_graph_create -- build the row schedule of a graph (degree binning) in caller memory.
  *   n, nnz          nodes and stored nonzeros (n >= 1, nnz >= 0).
  *   rowptr, col, w  device CSR arrays as described above; BORROWED: they must stay valid and
- *                   unchanged until pspec_graph_destroy.
+ *                   unchanged while the handle is used.
  *   wtype           element type of w.  F32 calls need PSPEC_F32 weights; F64 calls accept
  *                   either (FP32 weights are promoted exactly).
  *   k_max           largest k any later call on this handle will use (1..PSPEC_K_MAX).
+ *   workspace       device memory of ws_bytes >= pspec_graph_workspace_bytes(n, nnz, k_max) bytes,
+ *                   256-byte aligned, owned by the caller and BORROWED like the CSR (a smaller one
+ *                   returns PSPEC_ERR_WORKSPACE).  Its contents need no initialisation.
  *   stream          the schedule is built on this stream; the call synchronises it once to read
  *                   back the sizes of the schedule.
- *   out             receives the handle.
+ *   out             receives the handle (a small host object).
  * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
  * 16-lane group per row in node order; longer rows are cut into chunks of at most PSPEC_CHUNK
  * edges, handed out in a fixed order to one wavefront each, and rows spanning several chunks are
  * combined in a fixed order afterwards, so every result is bit-reproducible.  The CSR is
  * validated on the device (rowptr monotone with rowptr[0] = 0 and rowptr[n] = nnz, every column
- * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  The handle allocates its own device
- * memory (schedule, per-tile FP64 partial sums, chunk scratch): about
- * 8 * 4 * k_max * (n / 256 + 8 * CUs) bytes plus 8 * 2 * k_max + 32 bytes per chunk.
+ * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  No device memory is allocated.
  */
 #define PSPEC_LIGHT_MAX 32
 #define PSPEC_CHUNK 512
 pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
-                                const void *w, pspec_dtype wtype, int k_max, pspec_stream stream,
-                                pspec_graph *out);
+                                const void *w, pspec_dtype wtype, int k_max, void *workspace, size_t ws_bytes,
+                                pspec_stream stream, pspec_graph *out);
 
-/* Releases the handle's device memory (synchronises the device first).  NULL is a no-op. */
+/* Releases the handle (host memory only; no device call, no synchronisation).  The workspace and
+ * the CSR stay the caller's: they may be released once the work enqueued on the handle has
+ * completed.  NULL is a no-op. */
 pspec_status pspec_graph_destroy(pspec_graph g);
 
 /* Schedule statistics: rows above PSPEC_LIGHT_MAX, chunks, rows spanning several chunks. */
@@ -174,6 +199,19 @@ pspec_status pspec_hvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int6
 pspec_status pspec_hvp_sparse(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
                               int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
                               double *F_col, pspec_stream stream);
+
+/*
+ * pspec_hvp_gather_floor -- a MEASUREMENT REFERENCE, not part of the method: the FP32 edge pass of
+ * pspec_hvp (same kernels, launch geometry, schedule, neighbour gathers, row stores and reductions)
+ * with the arithmetic of every edge-column term replaced by a plain sum of the gathered values.
+ * Its duration bounds from below what any arithmetic of the same gathers can take, so the ratio of
+ * the two edge-pass times says how far the real pass is from its own memory floor.  HV and G
+ * receive meaningless values; the handle's per-column scalars are overwritten.  Arguments, layout
+ * and errors are those of pspec_hvp with dt = PSPEC_F32 (no p, eps or F_col).  The timing hook
+ * (pspec_graph_set_timing_events) brackets its edge pass as for pspec_hvp.
+ */
+pspec_status pspec_hvp_gather_floor(pspec_graph g, int k, const void *U, int64_t ldu, const void *V, int64_t ldv,
+                                    void *HV, int64_t ldh, void *G, int64_t ldg, pspec_stream stream);
 
 /*
  * Dense n x k operations of the Grassmann geometry (the manifold of Section 2; the formulas are

@@ -87,6 +87,8 @@ class Oracle:
         lib.oracle_error_scales.argtypes = [_i64, _i64p, _i32p, _f64p, ctypes.c_int, _f64p, _i64, _f64p, _i64,
                                             _dbl, _dbl, _f64p, _f64p, opt]
         lib.oracle_error_scales.restype = None
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         self.lib = lib
@@ -109,6 +111,10 @@ class Oracle:
 
     def num_threads(self) -> int:
         return int(self.lib.oracle_num_threads())
+
+    def set_num_threads(self, t: int) -> None:
+        """Threads of the later calls (the OpenMP row loops); sums over rows stay sequential."""
+        self.lib.oracle_set_num_threads(int(t))
 
     def objective(self, rowptr, col, w, U, p):
         """Returns (F, Fcol, Ncol, Dcol) of Eq. (1)."""

@@ -312,6 +312,16 @@ void oracle_error_scales(int64_t n, const int64_t *rowptr, const int32_t *col, c
     free(B);
 }
 
+/* Threads of the parallel regions that follow (ignored without OpenMP; t < 1 is taken as 1). */
+void oracle_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t < 1 ? 1 : t);
+#else
+    (void)t;
+#endif
+}
+
 /* Number of OpenMP threads a parallel region of this library uses (1 without OpenMP). */
 int oracle_num_threads(void)
 {

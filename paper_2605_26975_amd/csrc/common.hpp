@@ -41,7 +41,8 @@ void clear_error();
 // ---- row schedule ----------------------------------------------------------------------------
 // A heavy row (degree > PSPEC_LIGHT_MAX) is cut into chunks of at most PSPEC_CHUNK edges.  A chunk
 // whose row has a single chunk writes the row's results directly (slot = -1); otherwise it writes
-// partial rows into scratch slot `slot` and the row is combined afterwards (Split).
+// partial rows into scratch slot `slot` (its rank among the chunks of such rows) and the row is
+// combined afterwards from slots first .. first + count - 1 (Split).
 struct Chunk {
     int64_t beg, end;
     int32_t row, slot;
@@ -52,6 +53,7 @@ struct Split {
 
 constexpr int kBlock = 256;        // threads per workgroup of every kernel here
 constexpr int kHeavyPerCUMax = 8;  // most resident workgroups per CU of the persistent heavy-chunk kernel
+constexpr int kHeavyGridCap = 2048;  // most workgroups of the heavy-chunk kernel (8 per CU on 256 CUs)
 constexpr int kTileRows = 256;     // rows per light-kernel workgroup (one FP64 partial row each)
 constexpr int kQ = 4;              // FP64 partial sums per column: N, D, a = phi^T v, S_L = L^T v
 constexpr int kReduceSlices = 256; // first-stage workgroups of the deterministic reduction
@@ -69,7 +71,7 @@ struct Graph {
     int k_max = 0;
     int device = 0;
     int64_t tiles = 0;         // light tiles = ceil(n / kTileRows)
-    int64_t heavy_rows = 0, n_chunks = 0, n_split = 0;
+    int64_t heavy_rows = 0, n_chunks = 0, n_split = 0, n_split_chunks = 0;
     int64_t heavy_grid_max = 0;  // most workgroups of the heavy-chunk kernel (one partial row each)
     int cus = 1;                 // compute units of the device
     Chunk *chunks = nullptr;   // device [n_chunks]
@@ -77,8 +79,7 @@ struct Graph {
     double *partials = nullptr;   // device [(tiles + heavy_grid_max) * kQ * k_max]
     double *red1 = nullptr;       // device [kReduceSlices * kQ * k_max]
     double *scalars = nullptr;    // device [kScalars * k_max]
-    double *chunk_scratch = nullptr;  // device [n_chunks * 2 * k_max] (row partials of split rows)
-    void *mem = nullptr;          // the single device allocation holding all of the above
+    double *chunk_scratch = nullptr;  // device [n_split_chunks * 2 * k_max] (row partials of split rows)
     hipEvent_t ev_before = nullptr, ev_after = nullptr;  // optional edge-pass timing events
 };
 

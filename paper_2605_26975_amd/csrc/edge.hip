@@ -131,10 +131,18 @@ struct EdgeArgs {
 };
 
 // One edge-column term.  wv is the weight (0 for padding lanes, whose gather is the row itself).
-template <typename T, int MODE>
+// FLOOR: the gather-floor reference of the benchmark -- the same loads and stores with the
+// arithmetic replaced by a plain sum of the gathered values (the results are not the method's).
+template <typename T, int MODE, bool FLOOR = false>
 struct Term {
     __device__ __forceinline__ static void apply(const PowM2<T> &pw, T epsc, T ui, T uj, T vi, T vj, T wv, T &Ls,
                                                  T &Js, T &Ns) {
+        if constexpr (FLOOR) {
+            Ns += uj;
+            Ls += wv;
+            Js += vj;
+            return;
+        }
         const T x = ui - uj;
         const T h = pw(fabs(x));
         const T wh = wv * h;
@@ -218,7 +226,7 @@ constexpr int light_waves() {
     return (sizeof(T) == 4 && K == 32) ? 4 : 1;
 }
 
-template <typename T, typename WT, int K, int MODE>
+template <typename T, typename WT, int K, int MODE, bool FLOOR = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_waves<T, K>()))) void edge_light(EdgeArgs<T, WT> a) {
     constexpr int G = 16;
     constexpr int CPL = light_cpl<K>();  // columns per lane
@@ -341,7 +349,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                     const T wv = edge_bcast_val<T, G, EPR, u>(wl, e, lane);
 #pragma unroll
                     for (int m = 0; m < CPL; ++m)
-                        Term<T, MODE>::apply(a.pw, a.epsc, cur.ui[m], uj[u][m], cur.vi[m], vj[u][m], wv, Ls[m],
+                        Term<T, MODE, FLOOR>::apply(a.pw, a.epsc, cur.ui[m], uj[u][m], cur.vi[m], vj[u][m], wv, Ls[m],
                                              Js[m], Ns[m]);
                 }
             });
@@ -408,7 +416,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
 // writes the chunk's rows (or its scratch row when the row spans several chunks) and carries the
 // FP64 column sums of w |x|^p and L_i v_i from chunk to chunk.  Each workgroup writes one partial
 // row, its waves added in order, so the result does not depend on timing.
-template <typename T, typename WT, int K, int MODE, int UNR>
+template <typename T, typename WT, int K, int MODE, int UNR, bool FLOOR = false>
 __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t n_chunks) {
     constexpr int KW = K < 64 ? K : 64;  // column lanes of an edge slot
     constexpr int ES = 64 / KW;          // edge slots per wave
@@ -487,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
                 else vj[u] = T(0);
             }
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) Term<T, MODE>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wt[u], Ls, Js, Ns);
+            for (int u = 0; u < UNR; ++u)
+                Term<T, MODE, FLOOR>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wt[u], Ls, Js, Ns);
         }
         double L = (double)Ls, J = (double)Js, N = (double)Ns;
 #pragma unroll
@@ -833,7 +842,8 @@ int64_t heavy_grid(const Graph *g) {
         per_cu = v < kHeavyPerCUMax ? v : kHeavyPerCUMax;
     }
     const int64_t want = (g->n_chunks + 3) / 4, cap = (int64_t)per_cu * g->cus;
-    return want < cap ? want : cap;
+    const int64_t grid = want < cap ? want : cap;
+    return grid < g->heavy_grid_max ? grid : g->heavy_grid_max;  // the partial rows the workspace holds
 }
 
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
@@ -844,7 +854,7 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
 
 // The edge pass proper: edge kernels, split-row combine and the reductions to the per-column
 // scalars; L and J receive the raw rows.
-template <typename T, typename WT, int K, int MODE>
+template <typename T, typename WT, int K, int MODE, bool FLOOR = false>
 pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J, int64_t ldj,
                double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2 = true) {
     EdgeArgs<T, WT> a;
@@ -872,9 +882,10 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.k_max = g->k_max;
     a.part_base = g->tiles;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
-    edge_light<T, WT, K, MODE><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
+    edge_light<T, WT, K, MODE, FLOOR><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     const int64_t hb = heavy_grid<T, WT, K>(g);
-    if (hb > 0) edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>()><<<(unsigned)hb, kBlock, 0, s>>>(a, g->n_chunks);
+    if (hb > 0)
+        edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>(), FLOOR><<<(unsigned)hb, kBlock, 0, s>>>(a, g->n_chunks);
     if (g->n_split > 0 && MODE != OBJ)
         combine_split<T, MODE><<<grid_for(g->n_split * k, kBlock, 1 << 30), kBlock, 0, s>>>(
             g->splits, g->n_split, g->chunk_scratch, k, g->k_max, L, ldl, J, ldj);
@@ -1006,6 +1017,30 @@ pspec_status rhvp_k(Graph *g, int k, const void *U, int64_t ldu, const void *V, 
 #undef PSPEC_RHVP_K
 }
 
+// The gather-floor reference: the HVP edge pass (FP32 data, same kernels, grid, loads and stores)
+// with the arithmetic of every edge term replaced by a sum of the gathered values.
+pspec_status gather_floor(Graph *g, int k, const float *U, int64_t ldu, const float *V, int64_t ldv, float *L,
+                          int64_t ldl, float *J, int64_t ldj, hipStream_t s) {
+#define PSPEC_FLOOR_K(KK)                                                                                        \
+    case KK:                                                                                                     \
+        st = edge_pass<float, float, KK, HVP, true>(g, k, U, ldu, V, ldv, L, ldl, J, ldj, 1.5, 1.0, nullptr,      \
+                                                    nullptr, s);                                                 \
+        break;
+    pspec_status st = PSPEC_OK;
+    switch (pad_k(k)) {
+        PSPEC_FLOOR_K(4)
+        PSPEC_FLOOR_K(8)
+        PSPEC_FLOOR_K(16)
+        PSPEC_FLOOR_K(32)
+        PSPEC_FLOOR_K(64)
+        default: set_error("unsupported k = %d", k); return PSPEC_ERR_UNSUPPORTED;
+    }
+#undef PSPEC_FLOOR_K
+    if (st != PSPEC_OK) return st;
+    PSPEC_HIP(hipGetLastError());
+    return PSPEC_OK;
+}
+
 // Host-side argument checks shared by the entry points.
 pspec_status check_common(Graph *g, pspec_dtype dt, int k, const void *U, int64_t ldu, double p, const char *who) {
     PSPEC_ARG(g != nullptr, "%s: NULL graph", who);
@@ -1059,7 +1094,7 @@ extern "C" pspec_status pspec_grad(pspec_graph g, pspec_dtype dt, int k, const v
 
 static pspec_status hvp_entry(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
                               int64_t ldv, double p, double eps, void *HV, int64_t ldh, void *G, int64_t ldg,
-                              double *F_col, pspec_stream stream, bool rank2, const char *who) {
+                              double *F_col, pspec_stream stream, bool rank2, const char *who, bool floor = false) {
     clear_error();
     pspec_status st = check_common(g, dt, k, U, ldu, p, who);
     if (st != PSPEC_OK) return st;
@@ -1073,6 +1108,9 @@ static pspec_status hvp_entry(pspec_graph g, pspec_dtype dt, int k, const void *
                   !blocks_overlap(G, ldg, U, ldu, n, k, es) && !blocks_overlap(G, ldg, V, ldv, n, k, es) &&
                   !blocks_overlap(G, ldg, HV, ldh, n, k, es),
               "%s: HV and G must not overlap U, V or each other", who);
+    if (floor)
+        return gather_floor(g, k, (const float *)U, ldu, (const float *)V, ldv, (float *)G, ldg, (float *)HV, ldh,
+                            reinterpret_cast<hipStream_t>(stream));
     return dispatch<HVP>(g, dt, k, U, ldu, V, ldv, G, ldg, HV, ldh, p, eps, F_col, nullptr,
                          reinterpret_cast<hipStream_t>(stream), rank2);
 }
@@ -1087,6 +1125,14 @@ extern "C" pspec_status pspec_hvp_sparse(pspec_graph g, pspec_dtype dt, int k, c
                                          const void *V, int64_t ldv, double p, double eps, void *HV, int64_t ldh,
                                          void *G, int64_t ldg, double *F_col, pspec_stream stream) {
     return hvp_entry(g, dt, k, U, ldu, V, ldv, p, eps, HV, ldh, G, ldg, F_col, stream, false, "hvp_sparse");
+}
+
+extern "C" pspec_status pspec_hvp_gather_floor(pspec_graph g, int k, const void *U, int64_t ldu, const void *V,
+                                               int64_t ldv, void *HV, int64_t ldh, void *G, int64_t ldg,
+                                               pspec_stream stream) {
+    pspec_status st = hvp_entry(g, PSPEC_F32, k, U, ldu, V, ldv, 1.5, 1.0, HV, ldh, G, ldg, nullptr, stream, true,
+                                "hvp_gather_floor", true);
+    return st;
 }
 
 extern "C" pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,

@@ -3,13 +3,16 @@
 // Rows with at most PSPEC_LIGHT_MAX neighbours are processed in node order by the light edge
 // kernel (a group of lanes per row, kTileRows rows per workgroup).  Longer rows are cut into
 // chunks of at most PSPEC_CHUNK edges, handed in a fixed order to the waves of the persistent
-// heavy-chunk kernel; rows with several chunks are summed afterwards in chunk order.  The schedule is built with three integer kernels
-// (per-block counts, one-block exclusive scan, per-block emission with a block-local scan), so
-// chunk order, and with it every floating-point sum, is the same on every run.
+// heavy-chunk kernel; rows with several chunks are summed afterwards in chunk order.  The schedule is
+// built with three integer kernels (per-block counts, one-block exclusive scan, per-block emission
+// with a block-local scan), so chunk order, and with it every floating-point sum, is the same on every
+// run.  Everything the handle keeps on the device lives in the caller's workspace, whose size is
+// bounded from (n, nnz, k_max) alone; the library allocates no device memory.
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 
 #include "common.hpp"
 
@@ -42,7 +45,7 @@ bool blocks_overlap(const void *a, int64_t lda, const void *b, int64_t ldb, int6
 namespace {
 
 constexpr int kPlanBlock = 256;  // rows per block of the schedule kernels
-constexpr int kCounters = 3;     // heavy rows, chunks, split rows
+constexpr int kCounters = 4;     // heavy rows, chunks, split rows, chunks of split rows
 
 __global__ __launch_bounds__(kBlock) void k_check_rowptr(const int64_t *__restrict__ rowptr, int64_t n, int64_t nnz,
                                                        int *__restrict__ flag) {
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_check_col(const int32_t *__restrict_
 
 __device__ __forceinline__ void row_counts(const int64_t *__restrict__ rowptr, int64_t n, int64_t i, int light_max,
                                            int chunk, int64_t cnt[kCounters]) {
-    cnt[0] = cnt[1] = cnt[2] = 0;
+    cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
     if (i < n) {
         const int64_t d = rowptr[i + 1] - rowptr[i];
         if (d > light_max) {
@@ -76,6 +79,7 @@ __device__ __forceinline__ void row_counts(const int64_t *__restrict__ rowptr, i
             cnt[0] = 1;
             cnt[1] = nch;
             cnt[2] = nch > 1 ? 1 : 0;
+            cnt[3] = nch > 1 ? nch : 0;
         }
     }
 }
@@ -104,13 +108,13 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(int64_t *__restrict__ 
     const int t = threadIdx.x;
     const int64_t seg = (nb + kPlanBlock - 1) / kPlanBlock;
     const int64_t b0 = t * seg, b1 = (b0 + seg < nb) ? b0 + seg : nb;
-    int64_t loc[kCounters] = {0, 0, 0};
+    int64_t loc[kCounters] = {0, 0, 0, 0};
     for (int64_t b = b0; b < b1; ++b)
         for (int q = 0; q < kCounters; ++q) loc[q] += bcount[b * kCounters + q];
     for (int q = 0; q < kCounters; ++q) s[q][t] = loc[q];
     __syncthreads();
     if (t == 0) {
-        int64_t run[kCounters] = {0, 0, 0};
+        int64_t run[kCounters] = {0, 0, 0, 0};
         for (int i = 0; i < kPlanBlock; ++i)
             for (int q = 0; q < kCounters; ++q) {
                 const int64_t v = s[q][i];
@@ -151,6 +155,7 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restr
     if (cnt[1] == 0) return;
     const int64_t cbase = boff[(int64_t)blockIdx.x * kCounters + 1] + s[1][t] - cnt[1];
     const int64_t sbase = boff[(int64_t)blockIdx.x * kCounters + 2] + s[2][t] - cnt[2];
+    const int64_t xbase = boff[(int64_t)blockIdx.x * kCounters + 3] + s[3][t] - cnt[3];  // first scratch slot
     const int64_t beg = rowptr[i], end = rowptr[i + 1];
     const bool split = cnt[1] > 1;
     for (int64_t q = 0; q < cnt[1]; ++q) {
@@ -158,13 +163,13 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restr
         c.beg = beg + q * chunk;
         c.end = (c.beg + chunk < end) ? c.beg + chunk : end;
         c.row = (int32_t)i;
-        c.slot = split ? (int32_t)(cbase + q) : -1;
+        c.slot = split ? (int32_t)(xbase + q) : -1;
         chunks[cbase + q] = c;
     }
     if (split) {
         Split sp;
         sp.row = (int32_t)i;
-        sp.first = (int32_t)cbase;
+        sp.first = (int32_t)xbase;
         sp.count = (int32_t)cnt[1];
         sp.pad = 0;
         splits[sbase] = sp;
@@ -173,6 +178,49 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restr
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Layout of the caller's workspace: every part bounded from (n, nnz, k_max) alone.
+//   heavy rows   <= min(n, nnz / (LIGHT_MAX + 1))      (each holds more than LIGHT_MAX edges)
+//   chunks       <= nnz / CHUNK + heavy rows           (ceil(d / C) <= floor(d / C) + 1, sum floor <= nnz / C)
+//   split rows   <= min(n, nnz / (CHUNK + 1))
+//   split chunks <= nnz / CHUNK + split rows
+//   partial rows  = light tiles + kHeavyGridCap
+struct WsLayout {
+    size_t chunks = 0, splits = 0, part = 0, red1 = 0, sc = 0, scr = 0, bcount = 0, tot = 0, total = 0;
+    int64_t max_chunks = 0, max_split = 0, max_split_chunks = 0;
+};
+
+WsLayout ws_layout(int64_t n, int64_t nnz, int k_max) {
+    WsLayout L;
+    const int64_t max_heavy = std::min<int64_t>(n, nnz / (PSPEC_LIGHT_MAX + 1));
+    L.max_chunks = nnz / PSPEC_CHUNK + max_heavy;
+    L.max_split = std::min<int64_t>(n, nnz / (PSPEC_CHUNK + 1));
+    L.max_split_chunks = nnz / PSPEC_CHUNK + L.max_split;
+    const int64_t tiles = (n + kTileRows - 1) / kTileRows;
+    const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
+    const size_t parts[] = {
+        align256(sizeof(Chunk) * (size_t)L.max_chunks),
+        align256(sizeof(Split) * (size_t)L.max_split),
+        align256(sizeof(double) * (size_t)(tiles + kHeavyGridCap) * kQ * (size_t)k_max),
+        align256(sizeof(double) * (size_t)kReduceSlices * kQ * (size_t)k_max),
+        align256(sizeof(double) * (size_t)kScalars * (size_t)k_max),
+        align256(sizeof(double) * (size_t)L.max_split_chunks * 2 * (size_t)k_max),
+        align256(sizeof(int64_t) * (size_t)nb * kCounters),
+        align256(sizeof(int64_t) * kCounters + sizeof(int)),
+    };
+    size_t *dst[] = {&L.chunks, &L.splits, &L.part, &L.red1, &L.sc, &L.scr, &L.bcount, &L.tot};
+    size_t off = 0;
+    for (int i = 0; i < 8; ++i) {
+        *dst[i] = off;
+        off += parts[i];
+    }
+    L.total = off;
+    return L;
+}
+
+bool ws_args_ok(int64_t n, int64_t nnz, int k_max) {
+    return n >= 1 && nnz >= 0 && k_max >= 1 && k_max <= PSPEC_K_MAX && n < ((int64_t)1 << 31) - 1;
+}
+
 }  // namespace
 }  // namespace pspec
 
@@ -180,9 +228,13 @@ using namespace pspec;
 
 extern "C" const char *pspec_last_error(void) { return g_err; }
 
+extern "C" size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max) {
+    return ws_args_ok(n, nnz, k_max) ? ws_layout(n, nnz, k_max).total : 0;
+}
+
 extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
-                                           const void *w, pspec_dtype wtype, int k_max, pspec_stream stream,
-                                           pspec_graph *out) {
+                                           const void *w, pspec_dtype wtype, int k_max, void *workspace,
+                                           size_t ws_bytes, pspec_stream stream, pspec_graph *out) {
     clear_error();
     PSPEC_ARG(out != nullptr, "graph_create: out is NULL");
     *out = nullptr;
@@ -193,27 +245,23 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     PSPEC_ARG(wtype == PSPEC_F32 || wtype == PSPEC_F64, "graph_create: bad wtype %d", (int)wtype);
     PSPEC_UNSUP(k_max >= 1 && k_max <= PSPEC_K_MAX, "graph_create: k_max = %d outside 1..%d", k_max, PSPEC_K_MAX);
     PSPEC_UNSUP(n < ((int64_t)1 << 31) - 1, "graph_create: n = %lld needs 64-bit node ids", (long long)n);
+    PSPEC_ARG(workspace != nullptr, "graph_create: workspace is NULL");
+    PSPEC_ARG(((uintptr_t)workspace % 256) == 0, "graph_create: workspace must be 256-byte aligned");
+    const WsLayout L = ws_layout(n, nnz, k_max);
+    if (ws_bytes < L.total) {
+        set_error("graph_create: workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+        return PSPEC_ERR_WORKSPACE;
+    }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *mem = static_cast<char *>(workspace);
+    int64_t *bcount = reinterpret_cast<int64_t *>(mem + L.bcount);
+    int64_t *tot = reinterpret_cast<int64_t *>(mem + L.tot);
+    int *flag = reinterpret_cast<int *>(tot + kCounters);
 
     int dev = 0;
     PSPEC_HIP(hipGetDevice(&dev));
     const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
-    // temporary: per-block counters, totals, validation flag
-    const size_t tmp_bytes = align256((size_t)nb * kCounters * sizeof(int64_t)) + 256;
-    char *tmp = nullptr;
-    PSPEC_HIP(hipMalloc((void **)&tmp, tmp_bytes));
-    int64_t *bcount = reinterpret_cast<int64_t *>(tmp);
-    int64_t *tot = reinterpret_cast<int64_t *>(tmp + align256((size_t)nb * kCounters * sizeof(int64_t)));
-    int *flag = reinterpret_cast<int *>(tot + kCounters);
-
-    // On a failure the first error is the one reported; the frees on that path are best effort.
-    auto fail_hip = [&](const char *what, hipError_t e) {
-        set_error("graph_create: %s: %s", what, hipGetErrorString(e));
-        (void)hipFree(tmp);
-        return PSPEC_ERR_HIP;
-    };
-    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
-    if (e != hipSuccess) return fail_hip("hipMemsetAsync", e);
+    PSPEC_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     k_check_rowptr<<<(unsigned)((n + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(rowptr, n, nnz, flag);
     if (nnz > 0) {
         const int64_t want = (nnz + kBlock - 1) / kBlock;
@@ -221,19 +269,22 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     }
     k_plan_count<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount);
     k_plan_scan<<<1, kPlanBlock, 0, s>>>(bcount, nb, tot);
-    if ((e = hipGetLastError()) != hipSuccess) return fail_hip("schedule kernels", e);
+    PSPEC_HIP(hipGetLastError());
     int64_t host_tot[kCounters + 1];
-    if ((e = hipMemcpyAsync(host_tot, tot, sizeof(int64_t) * kCounters + sizeof(int), hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
-        return fail_hip("hipMemcpyAsync", e);
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip("hipStreamSynchronize", e);
+    PSPEC_HIP(hipMemcpyAsync(host_tot, tot, sizeof(int64_t) * kCounters + sizeof(int), hipMemcpyDeviceToHost, s));
+    PSPEC_HIP(hipStreamSynchronize(s));
     int host_flag = 0;
     std::memcpy(&host_flag, &host_tot[kCounters], sizeof(int));
     if (host_flag != 0) {
-        (void)hipFree(tmp);
         set_error("graph_create: malformed CSR (%s%s)", (host_flag & 1) ? "row pointers" : "",
                   (host_flag & 2) ? " column indices out of range" : "");
         return PSPEC_ERR_ARG;
+    }
+    // the bounds of ws_layout hold for every valid CSR; a violation means the counts are wrong
+    if (host_tot[1] > L.max_chunks || host_tot[2] > L.max_split || host_tot[3] > L.max_split_chunks) {
+        set_error("graph_create: schedule (%lld chunks, %lld split rows, %lld split chunks) exceeds its bound",
+                  (long long)host_tot[1], (long long)host_tot[2], (long long)host_tot[3]);
+        return PSPEC_ERR_HIP;
     }
 
     pspec_graph g = new pspec_graph_s();
@@ -249,55 +300,25 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->heavy_rows = host_tot[0];
     g->n_chunks = host_tot[1];
     g->n_split = host_tot[2];
+    g->n_split_chunks = host_tot[3];
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
     g->cus = cus > 0 ? cus : 1;
-    const int64_t hmax = (int64_t)kHeavyPerCUMax * g->cus, hwant = (g->n_chunks + 3) / 4;
-    g->heavy_grid_max = hwant < hmax ? hwant : hmax;
-    const int64_t P = g->tiles + g->heavy_grid_max;
-    const size_t b_chunks = align256(sizeof(Chunk) * (size_t)g->n_chunks);
-    const size_t b_splits = align256(sizeof(Split) * (size_t)g->n_split);
-    const size_t b_part = align256(sizeof(double) * (size_t)P * kQ * k_max);
-    const size_t b_red1 = align256(sizeof(double) * (size_t)kReduceSlices * kQ * k_max);
-    const size_t b_sc = align256(sizeof(double) * (size_t)kScalars * k_max);
-    const size_t b_scr = align256(sizeof(double) * (size_t)g->n_chunks * 2 * k_max);
-    const size_t total = b_chunks + b_splits + b_part + b_red1 + b_sc + b_scr;
-    char *mem = nullptr;
-    if ((e = hipMalloc((void **)&mem, total)) != hipSuccess) {
-        delete g;
-        return fail_hip("hipMalloc(schedule)", e);
-    }
-    g->mem = mem;
-    size_t off = 0;
-    g->chunks = reinterpret_cast<Chunk *>(mem + off);
-    off += b_chunks;
-    g->splits = reinterpret_cast<Split *>(mem + off);
-    off += b_splits;
-    g->partials = reinterpret_cast<double *>(mem + off);
-    off += b_part;
-    g->red1 = reinterpret_cast<double *>(mem + off);
-    off += b_red1;
-    g->scalars = reinterpret_cast<double *>(mem + off);
-    off += b_sc;
-    g->chunk_scratch = reinterpret_cast<double *>(mem + off);
-    if (g->n_chunks > 0) {
+    const int64_t hwant = (g->n_chunks + 3) / 4;
+    g->heavy_grid_max = std::min<int64_t>(std::min<int64_t>(hwant, (int64_t)kHeavyPerCUMax * g->cus), kHeavyGridCap);
+    g->chunks = reinterpret_cast<Chunk *>(mem + L.chunks);
+    g->splits = reinterpret_cast<Split *>(mem + L.splits);
+    g->partials = reinterpret_cast<double *>(mem + L.part);
+    g->red1 = reinterpret_cast<double *>(mem + L.red1);
+    g->scalars = reinterpret_cast<double *>(mem + L.sc);
+    g->chunk_scratch = reinterpret_cast<double *>(mem + L.scr);
+    if (g->n_chunks > 0)
         k_plan_emit<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount, g->chunks,
                                                          g->splits);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) {
-        (void)hipFree(mem);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
         delete g;
-        return fail_hip("k_plan_emit", e);
-    }
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
-        (void)hipFree(mem);
-        delete g;
-        return fail_hip("hipStreamSynchronize", e);
-    }
-    if ((e = hipFree(tmp)) != hipSuccess) {
-        (void)hipFree(mem);
-        delete g;
-        set_error("graph_create: hipFree: %s", hipGetErrorString(e));
+        set_error("graph_create: k_plan_emit: %s", hipGetErrorString(e));
         return PSPEC_ERR_HIP;
     }
     *out = g;
@@ -306,19 +327,7 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
 
 extern "C" pspec_status pspec_graph_destroy(pspec_graph g) {
     clear_error();
-    if (g == nullptr) return PSPEC_OK;
-    int cur = 0;
-    PSPEC_HIP(hipGetDevice(&cur));
-    PSPEC_HIP(hipSetDevice(g->device));
-    PSPEC_HIP(hipDeviceSynchronize());
-    const hipError_t e = hipFree(g->mem);
-    const hipError_t e2 = hipSetDevice(cur);  // restore the caller's device
-    delete g;
-    if (e != hipSuccess || e2 != hipSuccess) {
-        set_error("graph_destroy: %s: %s", e != hipSuccess ? "hipFree" : "hipSetDevice",
-                  hipGetErrorString(e != hipSuccess ? e : e2));
-        return PSPEC_ERR_HIP;
-    }
+    delete g;  // host memory only: the device memory is the caller's workspace
     return PSPEC_OK;
 }
 

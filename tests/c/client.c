@@ -49,6 +49,16 @@ int main(void) {
     st = pspec_kmeans_step(10, 40, PSPEC_F32, (void *)256, 40, 4, (const double *)512, NULL, NULL,
                            (double *)768, (void *)1024, (size_t)1 << 30, NULL);
     printf("kmeans d=40 -> %d (%s)\n", (int)st, pspec_last_error());
+    pspec_graph g = NULL;
+    st = pspec_graph_create(6, 10, (const int64_t *)256, (const int32_t *)512, (const void *)768, PSPEC_F32, 4,
+                            NULL, 0, NULL, &g);
+    printf("graph_create no workspace -> %d (%s)\n", (int)st, pspec_last_error());
+    st = pspec_graph_create(6, 10, (const int64_t *)256, (const int32_t *)512, (const void *)768, PSPEC_F32, 4,
+                            (void *)1024, 64, NULL, &g);
+    printf("graph_create small workspace -> %d (%s)\n", (int)st, pspec_last_error());
+    printf("graph workspace n=8000000 nnz=95998824 k=16: %zu bytes\n",
+           pspec_graph_workspace_bytes(8000000, 95998824, 16));
+    printf("graph workspace k=65: %zu bytes\n", pspec_graph_workspace_bytes(100, 100, 65));
     printf("dense workspace k=16: %zu bytes\n", pspec_dense_workspace_bytes(16));
     printf("kmeans workspace c=4 d=4: %zu bytes\n", pspec_kmeans_workspace_bytes(4, 4));
     return 0;

@@ -1,4 +1,5 @@
-/* A plain C client of libpspec.so on the GPU: device memory from the HIP runtime, a graph handle,
+/* A plain C client of libpspec.so on the GPU: device memory from the HIP runtime (including the graph
+ * handle's workspace, sized by pspec_graph_workspace_bytes), a graph handle,
  * F_p of Eq. (1) in FP64, checked against the C oracle (test infrastructure) on the same inputs.
  * No Python or torch.  Prints "ok" and the relative difference; tests/test_gpu_c_client.py runs it. */
 #include <hip/hip_runtime_api.h>
@@ -65,8 +66,12 @@ int main(void) {
     CHECK_HIP(hipMemcpy(d_w, w, sizeof(double) * nnz, hipMemcpyHostToDevice));
     CHECK_HIP(hipMemcpy(d_U, U, sizeof(double) * n * k, hipMemcpyHostToDevice));
 
+    /* the handle's schedule and scratch live in a workspace the caller allocates */
+    const size_t ws_bytes = pspec_graph_workspace_bytes(n, nnz, k);
+    void *d_ws = NULL;
+    CHECK_HIP(hipMalloc(&d_ws, ws_bytes));
     pspec_graph g = NULL;
-    pspec_status st = pspec_graph_create(n, nnz, d_rowptr, d_col, d_w, PSPEC_F64, k, NULL, &g);
+    pspec_status st = pspec_graph_create(n, nnz, d_rowptr, d_col, d_w, PSPEC_F64, k, d_ws, ws_bytes, NULL, &g);
     if (st != PSPEC_OK) {
         printf("graph_create: %d %s\n", (int)st, pspec_last_error());
         return 1;
@@ -84,6 +89,7 @@ int main(void) {
     const double rel = fabs(F - Fo) / fabs(Fo);
     printf("F gpu %.17g oracle %.17g rel %.3g\n", F, Fo, rel);
     pspec_graph_destroy(g);
+    CHECK_HIP(hipFree(d_ws));
     CHECK_HIP(hipFree(d_rowptr));
     CHECK_HIP(hipFree(d_col));
     CHECK_HIP(hipFree(d_w));

@@ -48,17 +48,27 @@ def test_binding_names_match_header():
 def test_host_side_argument_errors(libpspec):
     """Errors found before any launch: NULL output handle, bad sizes, bad k, NULL graph."""
     vp = ctypes.c_void_p
+    sz = ctypes.c_size_t
     libpspec.pspec_graph_create.argtypes = [ctypes.c_int64, ctypes.c_int64, vp, vp, vp, ctypes.c_int, ctypes.c_int,
-                                            vp, ctypes.POINTER(vp)]
+                                            vp, sz, vp, ctypes.POINTER(vp)]
     libpspec.pspec_graph_create.restype = ctypes.c_int
+    libpspec.pspec_graph_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    libpspec.pspec_graph_workspace_bytes.restype = sz
     libpspec.pspec_last_error.restype = ctypes.c_char_p
     h = vp()
-    assert libpspec.pspec_graph_create(0, 0, 1, 1, 1, 0, 4, None, ctypes.byref(h)) == 1
+    ws, big = 1 << 20, 1 << 40  # a 256-aligned stand-in address: nothing is dereferenced on these paths
+    assert libpspec.pspec_graph_create(0, 0, 1, 1, 1, 0, 4, ws, big, None, ctypes.byref(h)) == 1
     assert b"n = 0" in libpspec.pspec_last_error()
-    assert libpspec.pspec_graph_create(10, -1, 1, 1, 1, 0, 4, None, ctypes.byref(h)) == 1
-    assert libpspec.pspec_graph_create(10, 5, None, 1, 1, 0, 4, None, ctypes.byref(h)) == 1
-    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 65, None, ctypes.byref(h)) == 2
-    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, None, None) == 1
+    assert libpspec.pspec_graph_create(10, -1, 1, 1, 1, 0, 4, ws, big, None, ctypes.byref(h)) == 1
+    assert libpspec.pspec_graph_create(10, 5, None, 1, 1, 0, 4, ws, big, None, ctypes.byref(h)) == 1
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 65, ws, big, None, ctypes.byref(h)) == 2
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, ws, big, None, None) == 1
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, None, big, None, ctypes.byref(h)) == 1
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, ws + 8, big, None, ctypes.byref(h)) == 1
+    assert b"aligned" in libpspec.pspec_last_error()
+    need = libpspec.pspec_graph_workspace_bytes(10, 5, 4)
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, ws, need - 1, None, ctypes.byref(h)) == 4
+    assert libpspec.pspec_graph_workspace_bytes(0, 5, 4) == 0 and libpspec.pspec_graph_workspace_bytes(10, 5, 65) == 0
     libpspec.pspec_objective.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, ctypes.c_double, vp, vp,
                                          vp]
     libpspec.pspec_objective.restype = ctypes.c_int
@@ -122,3 +132,66 @@ def test_kmeans_host_side_errors(libpspec):
     assert call(100, 4, 0, 256, 4, 4, 512, None, None, 768, 1000, ws, None) == 1
     assert call(100, 4, 0, 256, 4, 4, 512, None, None, 768, 1024, ws - 8, None) == 4
     assert b"workspace" in libpspec.pspec_last_error()
+
+
+def test_graph_workspace_bound_covers_every_schedule():
+    """pspec_graph_workspace_bytes bounds the schedule from (n, nnz, k_max) alone: it grows with each
+    and covers the worst degree patterns (every row just above the light limit, one giant row)."""
+    lib = ctypes.CDLL(LIB)
+    f = lib.pspec_graph_workspace_bytes
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    f.restype = ctypes.c_size_t
+    n, nnz = 1000, 33 * 1000
+    chunk, light = 512, 32
+    base = f(n, nnz, 8)
+    assert f(n, nnz, 16) > base and f(n, 2 * nnz, 8) > base and f(2 * n, nnz, 8) > base
+    # all rows of degree 33: 1000 heavy rows, 1000 chunks of 24 bytes; one row of degree 33000: 65 chunks,
+    # all of them split chunks with 2 k_max doubles of scratch each
+    worst_chunks = max(n, -(-nnz // chunk))
+    assert base >= 24 * worst_chunks + 16 * worst_chunks + 2 * 8 * 8 * (-(-nnz // chunk))
+    assert f(n, 0, 8) > 0  # an empty graph still needs its partial sums
+
+
+def test_binding_rejects_mismatched_blocks(monkeypatch):
+    """The binding is the guard in front of a pointer-only ABI: every block must have the graph's n
+    rows, the same k, dtype and device, and scalar outputs the right size, before any call is made.
+    Exercised with host tensors standing in for device ones (the checks raise before the library is
+    reached, so no GPU is needed)."""
+    import torch
+
+    from paper_2605_26975_amd import pspec
+
+    monkeypatch.setattr(pspec, "_on_device", lambda t: isinstance(t, torch.Tensor))
+
+    class FakeGraph:
+        n, k_max, device = 100, 8, torch.device("cpu")
+        handle = None
+
+    g = FakeGraph()
+    U = torch.zeros(100, 8)
+    bad = {
+        "short U": lambda: pspec.objective(g, torch.zeros(99, 8), 1.5),
+        "k above k_max": lambda: pspec.objective(g, torch.zeros(100, 9), 1.5),
+        "short V": lambda: pspec.hvp(g, U, torch.zeros(99, 8), 1.5),
+        "V with other k": lambda: pspec.hvp(g, U, torch.zeros(100, 7), 1.5),
+        "V float64": lambda: pspec.hvp(g, U, torch.zeros(100, 8, dtype=torch.float64), 1.5),
+        "short G": lambda: pspec.grad(g, U, 1.5, G=torch.zeros(50, 8)),
+        "HV float64": lambda: pspec.hvp(g, U, U.clone(), 1.5, HV=torch.zeros(100, 8, dtype=torch.float64)),
+        "F_col too short": lambda: pspec.hvp(g, U, U.clone(), 1.5, F_col=torch.zeros(7, dtype=torch.float64)),
+        "F_col float32": lambda: pspec.objective(g, U, 1.5, F_col=torch.zeros(8)),
+        "RH short": lambda: pspec.rhvp(g, U, U.clone(), 1.5, RH=torch.zeros(10, 8)),
+        "MG wrong size": lambda: pspec.rhvp(g, U, U.clone(), 1.5, MG=torch.zeros(4, 4, dtype=torch.float64)),
+        "Z other k": lambda: pspec.project(U, torch.zeros(100, 4)),
+        "X without MX": lambda: pspec.project(U, U.clone(), X=U.clone()),
+        "out short": lambda: pspec.project(U, U.clone(), out=torch.zeros(100, 4)),
+        "eta float64": lambda: pspec.retract(U, torch.zeros(100, 8, dtype=torch.float64), 0.1),
+        "dot mismatch": lambda: pspec.dot(U, torch.zeros(100, 9)),
+        "axpby mismatch": lambda: pspec.axpby(1.0, torch.zeros(90, 8), 0.0, U),
+        "int block": lambda: pspec.dot(torch.zeros(100, 8, dtype=torch.int32), torch.zeros(100, 8, dtype=torch.int32)),
+        "overlapping rows": lambda: pspec.dot(torch.zeros(800).as_strided((100, 8), (4, 1)), U),
+        "column-major": lambda: pspec.dot(torch.zeros(8, 100).t(), U),
+    }
+    for what, call in bad.items():
+        with pytest.raises(pspec.PSpecArgError):
+            call()
+            pytest.fail(what)

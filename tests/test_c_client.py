@@ -27,5 +27,10 @@ def test_c_client_links_and_runs(tmp_path):
     assert "rcm bandwidth 1" in out
     assert "project n=0 -> 1" in out
     assert "kmeans d=40 -> 2" in out
+    assert "graph_create no workspace -> 1" in out
+    assert "graph_create small workspace -> 4" in out
+    assert "graph workspace k=65: 0 bytes" in out
+    gws = int(out.split("graph workspace n=8000000 nnz=95998824 k=16: ")[1].split()[0])
+    assert 150e6 < gws < 250e6
     ws = int(out.split("dense workspace k=16: ")[1].split()[0])
     assert ws >= 2 * 1024 * 16 * 16 * 8
