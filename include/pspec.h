@@ -264,6 +264,23 @@ pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int
                         int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
                         double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream);
 
+/*
+ * pspec_rhvp_static -- pspec_rhvp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): no workspace argument; the
+ * Gram partials and k x k matrices live in a file-scope device array of the library, one per GPU,
+ * of pspec_dense_workspace_bytes(PSPEC_STATIC_K_MAX) bytes (17,318,400 bytes, held by every GPU the library
+ * runs on until the process ends).  Results are identical to pspec_rhvp's, bit for bit.
+ *   k    1..PSPEC_STATIC_K_MAX; a wider block returns PSPEC_ERR_UNSUPPORTED.
+ * Every call on one GPU uses that GPU's single array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.  The array keeps the last
+ * call's contents; nothing in it needs clearing between calls.  Other arguments, layout and errors
+ * are those of pspec_rhvp.  The graph handle's own workspace is the caller's, as always.
+ */
+#define PSPEC_STATIC_K_MAX 32
+pspec_status pspec_rhvp_static(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                               int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
+                               double *MG, double *F_col, pspec_stream stream);
+
 /* pspec_dot -- *out = sum_{i,l} A[i,l] B[i,l] (Frobenius inner product, FP64, fixed order). */
 pspec_status pspec_dot(int64_t n, int k, pspec_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb,
                        double *out, void *ws, size_t ws_bytes, pspec_stream stream);

@@ -19,7 +19,7 @@ constexpr int kTreeFan = 32;         // partials summed per thread at each furth
 // Workspace (doubles) of the dense operations: room for two k x k matrices at every level, i.e.
 // level-1 partials [kDenseBlocks][2][k*k], level-2 partials [kDenseBlocks / kTreeFan][2][k*k] and
 // two reduced matrices (M, R^-1 or U^T G, U^T HV), plus slack.
-inline size_t dense_ws_doubles(int k) {
+constexpr size_t dense_ws_doubles(int k) {
     const size_t kk2 = 2 * (size_t)k * k;
     return kDenseBlocks * kk2 + (kDenseBlocks / kTreeFan) * kk2 + kk2 + 64;
 }

@@ -18,6 +18,7 @@
 // the sparse-only Hessian (pspec_hvp_sparse) sets a = b = 0, dropping the rank-2 term.  The
 // Riemannian call (pspec_rhvp) fuses the epilogue with both projections for 16 <= k <= 32.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1066,6 +1067,33 @@ pspec_status check_out(Graph *g, pspec_dtype dt, int k, const void *X, int64_t l
     return PSPEC_OK;
 }
 
+// ---- the allocation-free Riemannian call ----------------------------------------------------
+// The dense workspace of pspec_rhvp_static is a file-scope device array, one copy per GPU, sized for
+// k <= PSPEC_STATIC_K_MAX.  Host code never passes its name to a kernel: the device address of each
+// GPU's copy comes from hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[dense_ws_doubles(PSPEC_STATIC_K_MAX)];
+std::mutex g_scratch_mutex;
+double *g_scratch_addr[kMaxDevices] = {};
+
+pspec_status static_scratch(double **out, const char *who) {
+    int dev = 0;
+    PSPEC_HIP(hipGetDevice(&dev));
+    PSPEC_UNSUP(dev >= 0 && dev < kMaxDevices, "%s: device %d outside 0..%d", who, dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_addr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("%s: hipGetSymbolAddress(scratch) on device %d: %s", who, dev, hipGetErrorString(e));
+            return PSPEC_ERR_HIP;
+        }
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return PSPEC_OK;
+}
+
 }  // namespace
 }  // namespace pspec
 
@@ -1163,4 +1191,18 @@ extern "C" pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const v
     if (g->wtype == PSPEC_F32)
         return rhvp_k<double, float>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
     return rhvp_k<double, double>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
+}
+
+extern "C" pspec_status pspec_rhvp_static(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu,
+                                          const void *V, int64_t ldv, double p, double eps, void *RH, int64_t ldrh,
+                                          void *RG, int64_t ldrg, double *MG, double *F_col, pspec_stream stream) {
+    clear_error();
+    PSPEC_UNSUP(k >= 1 && k <= PSPEC_STATIC_K_MAX,
+                "rhvp_static: k = %d outside 1..%d (the static scratch holds the Gram partials of k <= %d)", k,
+                PSPEC_STATIC_K_MAX, PSPEC_STATIC_K_MAX);
+    double *ws = nullptr;
+    const pspec_status st = static_scratch(&ws, "rhvp_static");
+    if (st != PSPEC_OK) return st;
+    return pspec_rhvp(g, dt, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws,
+                      dense_ws_doubles(PSPEC_STATIC_K_MAX) * sizeof(double), stream);
 }

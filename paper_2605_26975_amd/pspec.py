@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
         "pspec_hvp_sparse": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp],
         "pspec_hvp_gather_floor": [vp, i32, vp, i64, vp, i64, vp, i64, vp, i64, vp],
         "pspec_rhvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp, sz, vp],
+        "pspec_rhvp_static": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp],
         "pspec_project": [i64, i32, i32, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, sz, vp],
         "pspec_retract": [i64, i32, i32, vp, i64, vp, i64, dbl, vp, i64, vp, vp, sz, vp],
         "pspec_dot": [i64, i32, i32, vp, i64, vp, i64, vp, vp, sz, vp],
@@ -88,7 +89,7 @@ def exported_symbols() -> list[str]:
         "pspec_graph_workspace_bytes", "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info",
         "pspec_graph_set_timing_events",
         "pspec_objective", "pspec_grad",
-        "pspec_hvp", "pspec_hvp_sparse", "pspec_hvp_gather_floor", "pspec_rhvp", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
+        "pspec_hvp", "pspec_hvp_sparse", "pspec_hvp_gather_floor", "pspec_rhvp", "pspec_rhvp_static", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
         "pspec_axpby", "pspec_kmeans_workspace_bytes", "pspec_kmeans_step", "pspec_rcm_order",
         "pspec_last_error",
     ]
@@ -333,6 +334,27 @@ def rhvp(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float = 
     _check(lib().pspec_rhvp(graph.handle, _dtype_code(U), k, U.data_ptr(), ldu, V.data_ptr(), ldv, float(p),
                             float(eps), RH.data_ptr(), RH.stride(0), RG.data_ptr(), RG.stride(0),
                             MG.data_ptr(), F_col.data_ptr(), ws.data_ptr(), ws.numel(), _stream(U.device)))
+    return RH, RG, MG, F_col
+
+
+STATIC_K_MAX = 32
+
+
+def rhvp_static(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float, RH: torch.Tensor,
+                RG: torch.Tensor, MG: torch.Tensor, F_col: torch.Tensor):
+    """pspec_rhvp_static: rhvp with the library's per-GPU static scratch instead of a workspace, for
+    callers that cannot allocate (k <= STATIC_K_MAX).  Every output is the caller's: this wrapper
+    allocates nothing.  Calls that overlap on one GPU race (one scratch array per GPU)."""
+    ldu = _on_graph(graph, U)
+    ldv = _block(V, "V", like=U)
+    k = U.shape[1]
+    _block(RH, "RH", like=U)
+    _block(RG, "RG", like=U)
+    _fp64_vec(MG, "MG", k * k, U.device)
+    _fp64_vec(F_col, "F_col", k, U.device)
+    _check(lib().pspec_rhvp_static(graph.handle, _dtype_code(U), k, U.data_ptr(), ldu, V.data_ptr(), ldv, float(p),
+                                   float(eps), RH.data_ptr(), RH.stride(0), RG.data_ptr(), RG.stride(0),
+                                   MG.data_ptr(), F_col.data_ptr(), _stream(U.device)))
     return RH, RG, MG, F_col
 
 
