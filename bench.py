@@ -34,12 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "p-Laplacian grad+HVP edge·col updates/s, FP32 vs FP64, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "edge_hvp_sbm8m_traffic.json")
-VALU_FILE = os.path.join(PROFILES, "edge_hvp_sbm8m_valu.json")
-VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FLOPS_FP32_TRANS", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_SALU",
-                 "SQ_INSTS_LDS", "SQ_BUSY_CU_CYCLES")
 CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
-EDGE_KERNEL = "edge_light<float, float, 16, 2>"  # the fused grad+HVP edge pass at k = 16
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read and 1 GiB written
 WORKLOADS = {
     "sbm8m": "sbm8m: SBM n=8,000,000, 16 blocks, mean degree 12, w~U[0.5,1.5], k=16, p=1.1, eps=1e-8",
@@ -69,77 +64,170 @@ def algorithmic_edge_bytes(n: int, nnz: int, k: int, es: int = 4) -> int:
     return nnz * (4 + es) + (n + 1) * 8 + n * k * es * 4
 
 
-def stored_traffic(workload: str, layout: str):
-    """HBM bytes per launch of the edge kernel from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("source_hash") != edge_source_hash() or t.get("workload") != workload or t.get("layout") != layout:
-        return None
-    return t.get("bytes_per_launch")
+def _pad_k(k: int) -> int:
+    K = 4
+    while K < k:
+        K *= 2
+    return K
 
 
-def stored_valu(workload: str, layout: str, edge_ms: float):
-    """The VALU ceiling of the edge kernel from the committed counter summary (same source check as
-    the traffic): issue time of its VALU instructions (a wave64 instruction occupies a 16-lane SIMD
-    for 4 cycles; 4 SIMDs per CU; transcendentals counted at full rate, so a lower bound) against
-    the measured launch time, and the measured VALU busy fraction."""
+def _short(name: str) -> str:
+    return name.replace("pspec::(anonymous namespace)::", "").replace("void ", "", 1).split("(")[0]
+
+
+def is_edge_pass_kernel(name: str, k: int) -> bool:
+    """The kernels of the FP32 grad+HVP edge pass at width k: light rows, heavy chunks, split-row
+    combine (not the gather-floor reference, whose last template argument is true)."""
+    nm, K = _short(name), _pad_k(k)
+    return (nm == f"edge_light<float, float, {K}, 2, false>" or
+            (nm.startswith(f"edge_heavy<float, float, {K}, 2, ") and nm.endswith(", false>")) or
+            nm == "combine_split<float, 2>")
+
+
+def _stored(kind: str, workload: str, layout: str):
     try:
-        with open(VALU_FILE) as f:
+        with open(os.path.join(PROFILES, f"edge_hvp_{workload}_{kind}.json")) as f:
             v = json.load(f)
     except (OSError, ValueError):
         return None
     if v.get("source_hash") != edge_source_hash() or v.get("workload") != workload or v.get("layout") != layout:
         return None
-    ceiling_ms = v["valu_issue_ms"]
-    return {"bound": "alu", "valu_issue_ms": ceiling_ms, "frac": ceiling_ms / edge_ms,
-            "valu_busy": v["valu_busy"], "valu_insts_per_edge_col": v["valu_insts_per_edge_col"]}
+    return v
 
 
-def summarize_valu(pmc_dir: str, cmd: str, nnz: int, k: int) -> None:
-    """Write the VALU summary of the edge kernel from one rocprofv3 --pmc run of VALU_COUNTERS."""
+def stored_traffic(workload: str, layout: str):
+    """HBM bytes per edge pass (all its kernels) from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    v = _stored("traffic", workload, layout)
+    return None if v is None else v.get("bytes_per_launch")
+
+
+def stored_valu(workload: str, layout: str, edge_ms: float):
+    """The VALU figures of the edge pass from the committed counter summary (same source check as the
+    traffic): issue time of its VALU instructions (a wave64 instruction occupies a 16-lane SIMD for 4
+    cycles, 4 SIMDs per CU; transcendentals at a quarter of the rate) against the measured pass, and
+    the measured VALU busy fraction."""
+    v = _stored("valu", workload, layout)
+    if v is None:
+        return None
+    return {"bound": "alu", "valu_issue_ms": v["valu_issue_ms"], "frac": v["valu_issue_ms"] / edge_ms,
+            "valu_busy": v["valu_busy"], "valu_insts_per_edge_col": v["valu_insts_per_edge_col"],
+            "trans_insts_per_edge_col": v.get("trans_insts_per_edge_col")}
+
+
+def _csv_rows(pattern):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(pattern, recursive=True)):
+        with open(f) as fh:
+            rows.extend({k.lower(): v for k, v in r.items()} for r in csv.DictReader(fh))
+    return rows
+
+
+def _per_kernel(rows):
+    """{kernel: {counter: median per dispatch}} and {kernel: median dispatch ms} from counter rows."""
     import statistics
 
-    rows = _csv_rows(os.path.join(pmc_dir, "**", "*counter_collection.csv"))
-    is_edge = lambda nm: EDGE_KERNEL in nm.replace("pspec::(anonymous namespace)::", "")  # noqa: E731
-    med = {}
-    durs = {}
+    vals, durs = {}, {}
     for r in rows:
-        if not is_edge(r["kernel_name"]):
-            continue
-        med.setdefault(r["counter_name"], []).append(float(r["counter_value"]))
-        durs[r["dispatch_id"]] = (float(r["end_timestamp"]) - float(r["start_timestamp"])) * 1e-6
-    med = {c: statistics.median(v) for c, v in med.items()}
-    dur_ms = statistics.median(durs.values())
-    valu = med["SQ_INSTS_VALU"]  # wave64 instructions, summed over the SIMDs of every SE
-    # issue cycles per CU: 4 cycles per wave64 VALU instruction on one of its 4 SIMDs
-    issue_ms = valu * 4 / 4 / CUS / CLOCK_HZ * 1e3
-    # rocprofv3's VALUBusy: SQ_ACTIVE_INST_VALU (quad-cycles summed over SIMDs) / CUs / cycles
-    busy = med["SQ_ACTIVE_INST_VALU"] / CUS / (CLOCK_HZ * dur_ms * 1e-3)
-    out = {
-        "workload": "sbm8m", "layout": "interleaved", "kernel": EDGE_KERNEL, "source_hash": edge_source_hash(),
-        "counters_per_dispatch": med, "dispatch_ms_under_counters": dur_ms,
-        "valu_insts_per_edge_col": valu * 64 / (nnz * k), "valu_issue_ms": issue_ms, "valu_busy": busy,
-        "command": cmd,
-    }
-    with open(VALU_FILE, "w") as f:
-        json.dump(out, f, indent=1)
-    md = ["# VALU work of the fused grad+HVP edge pass: SBM n=8,000,000, k=16, FP32", "",
-          "Counter run (from the repository root, one MI355X):", "", "```", cmd, "```", "",
-          "| quantity | value |", "|---|---|"]
-    md += [f"| {c} (per dispatch, median) | {v:.6g} |" for c, v in med.items()]
-    md += [f"| dispatch time under counters (ms) | {dur_ms:.4g} |",
-           f"| VALU lane-instructions per edge-col | {out['valu_insts_per_edge_col']:.4g} |",
-           f"| VALU issue time at {CUS} CUs x {CLOCK_HZ / 1e9:.1f} GHz, all at full rate (ms) | {issue_ms:.4g} |",
-           f"| VALU busy (rocprofv3 VALUBusy: SQ_ACTIVE_INST_VALU / CUs / cycles) | {busy:.3f} |", "",
-           "SQ_INSTS_VALU_FLOPS_FP32_TRANS reads 0.04 per edge-col where the kernel issues one v_log_f32 and "
-           "one v_exp_f32 per edge-col: that counter does not count them here, so the issue time takes "
-           "every VALU instruction at full rate (a lower bound; the two transcendentals run at quarter rate)."]
-    with open(os.path.join(PROFILES, "edge_hvp_sbm8m_valu.md"), "w") as f:
-        f.write("\n".join(md) + "\n")
+        nm = _short(r["kernel_name"])
+        vals.setdefault(nm, {}).setdefault(r["counter_name"], []).append(float(r["counter_value"]))
+        durs.setdefault(nm, {})[r["dispatch_id"]] = (float(r["end_timestamp"]) - float(r["start_timestamp"])) * 1e-6
+    med = {nm: {c: statistics.median(v) for c, v in cs.items()} for nm, cs in vals.items()}
+    ms = {nm: statistics.median(d.values()) for nm, d in durs.items()}
+    return med, ms
+
+
+def summarize_pmc(workload: str, nnz: int, k: int, out_name: str, runs: list) -> None:
+    """Write profiles/<out_name>.md from rocprofv3 --pmc runs (each "DIR::COMMAND"): per-kernel medians
+    of every counter for the edge-pass kernels, the Gram kernels and the calibration copy, and what
+    follows from them -- HBM traffic per edge pass (FETCH_SIZE, WRITE_SIZE scaled by what they read
+    for the 1 GiB copy; saved to edge_hvp_<workload>_traffic.json), VALU and transcendental
+    instructions per edge-col (edge_hvp_<workload>_valu.json), L2 hit rates, FP64 matrix-core use."""
+    med, ms = {}, {}
+    cmds = []
+    for run in runs:
+        d, cmd = run.split("::", 1)
+        cmds.append(cmd)
+        m, t = _per_kernel(_csv_rows(os.path.join(d, "**", "*counter_collection.csv")))
+        for nm, cs in m.items():
+            med.setdefault(nm, {}).update(cs)
+            ms[nm] = t[nm]
+    edge = [nm for nm in med if is_edge_pass_kernel(nm, k)]
+    gram = [nm for nm in med if nm.startswith(("finalize_gram", "apply_rhvp", "gram_partial", "apply_rows"))]
+    copy = [nm for nm in med if nm.startswith("axpby_k<float, 16, true>")]
+    layout, lines = "interleaved", []
+    lines += [f"# Counters: {workload} (nnz = {nnz}, k = {k}), FP32", "",
+              "Counter runs (from the repository root, one MI355X, one counter group per run):", "", "```"]
+    lines += cmds + ["```", "", "Per-dispatch medians.", "", "| kernel | ms | counter | value |", "|---|---|---|---|"]
+    for nm in edge + gram + copy:
+        for c, v in sorted(med[nm].items()):
+            lines.append(f"| `{nm[:70]}` | {ms[nm]:.4g} | {c} | {v:.6g} |")
+    lines.append("")
+    edge_ms = sum(ms[nm] for nm in edge)
+    kib = COPY_BYTES / 1024.0
+    have = lambda c, nms: all(c in med[nm] for nm in nms) and nms  # noqa: E731
+    if have("FETCH_SIZE", edge) and have("WRITE_SIZE", edge) and copy and "FETCH_SIZE" in med[copy[0]] \
+            and "WRITE_SIZE" in med[copy[0]]:
+        fs, ws = kib / med[copy[0]]["FETCH_SIZE"], kib / med[copy[0]]["WRITE_SIZE"]
+        fetch = sum(med[nm]["FETCH_SIZE"] for nm in edge)
+        write = sum(med[nm]["WRITE_SIZE"] for nm in edge)
+        traffic = (fetch * fs + write * ws) * 1024.0
+        out = {"workload": workload, "layout": layout, "kernels": edge, "source_hash": edge_source_hash(),
+               "fetch_kib_per_pass": fetch, "write_kib_per_pass": write, "fetch_scale": fs, "write_scale": ws,
+               "bytes_per_launch": traffic, "commands": cmds}
+        with open(os.path.join(PROFILES, f"edge_hvp_{workload}_traffic.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        lines += [f"HBM traffic of the edge pass ({', '.join(f'`{e}`' for e in edge)}): FETCH_SIZE {fetch:.6g} KiB "
+                  f"x {fs:.4f} + WRITE_SIZE {write:.6g} KiB x {ws:.4f} = {traffic / 1e9:.3f} GB per pass (the scales "
+                  f"are known KiB / counted KiB of a plain 1 GiB device copy in the same runs); "
+                  f"{traffic / (nnz * k):.3f} B per edge-col; {traffic / (edge_ms * 1e-3) / 1e9:.0f} GB/s over "
+                  f"the pass's {edge_ms:.3f} ms under counters.", ""]
+    if have("SQ_INSTS_VALU", edge):
+        valu = sum(med[nm]["SQ_INSTS_VALU"] for nm in edge)
+        trans = sum(med[nm].get("SQ_INSTS_VALU_TRANS_F32", 0.0) for nm in edge)
+        # issue cycles per CU: 4 per wave64 VALU instruction on one of 4 SIMDs; transcendentals 4x that
+        issue_ms = (valu + 3 * trans) * 4 / 4 / CUS / CLOCK_HZ * 1e3
+        busy_num = sum(med[nm].get("SQ_ACTIVE_INST_VALU", 0.0) for nm in edge)
+        busy = busy_num / CUS / (CLOCK_HZ * edge_ms * 1e-3)
+        out = {"workload": workload, "layout": layout, "kernels": edge, "source_hash": edge_source_hash(),
+               "valu_insts_per_edge_col": valu * 64 / (nnz * k), "trans_insts_per_edge_col": trans * 64 / (nnz * k),
+               "valu_issue_ms": issue_ms, "valu_busy": busy, "dispatch_ms_under_counters": edge_ms, "commands": cmds}
+        with open(os.path.join(PROFILES, f"edge_hvp_{workload}_valu.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        lines += [f"VALU of the edge pass: {out['valu_insts_per_edge_col']:.3g} lane-instructions per edge-col, of "
+                  f"which {out['trans_insts_per_edge_col']:.3g} transcendental (SQ_INSTS_VALU_TRANS_F32); issue time "
+                  f"{issue_ms:.3f} ms at {CUS} CUs x {CLOCK_HZ / 1e9:.1f} GHz (transcendentals at quarter rate) "
+                  f"against {edge_ms:.3f} ms; VALU busy (SQ_ACTIVE_INST_VALU / CUs / cycles) {busy:.2f}.", ""]
+    for nm in edge + gram:
+        cs = med[nm]
+        if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
+            h, m = cs["TCC_HIT_sum"], cs["TCC_MISS_sum"]
+            lines.append(f"L2 hit rate of `{nm}`: {h / max(h + m, 1):.3f} ({h:.4g} hits, {m:.4g} misses).")
+        if "SQ_INSTS_VALU_MFMA_MOPS_F64" in cs:
+            flops = cs["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512
+            lines.append(f"FP64 matrix cores in `{nm}`: {flops / 1e9:.3g} GFLOP per dispatch (MOPS x 512), "
+                         f"{flops / (ms[nm] * 1e-3) / 1e12:.2f} TFLOP/s = "
+                         f"{flops / (ms[nm] * 1e-3) / 78.6e12:.1%} of the 78.6 TFLOP/s FP64 peak"
+                         + (f"; MFMA busy {cs['SQ_VALU_MFMA_BUSY_CYCLES'] / (CUS * CLOCK_HZ * ms[nm] * 1e-3):.1%} of "
+                            f"CU cycles." if "SQ_VALU_MFMA_BUSY_CYCLES" in cs else "."))
+    with open(os.path.join(PROFILES, f"{out_name}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def summarize_trace(trace_dir: str, workload: str, cmd: str, out_name: str) -> None:
+    """Write profiles/<out_name>.md: the kernel statistics of a rocprofv3 --kernel-trace --stats run."""
+    stats = _csv_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    lines = [f"# Kernel trace: {WORKLOADS.get(workload, workload)}", "",
+             "Command (from the repository root, on one MI355X):", "", "```", cmd, "```", "",
+             "| kernel | calls | average us | share % |", "|---|---|---|---|"]
+    for r in stats[:16]:
+        lines.append(f"| `{_short(r['name'])[:80]}` | {r['calls']} | {float(r['averagens']) / 1e3:.1f} | "
+                     f"{float(r['percentage']):.1f} |")
+    with open(os.path.join(PROFILES, f"{out_name}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 class HipEvents:
@@ -171,85 +259,6 @@ class HipEvents:
         for a, b in self.pairs:
             self.hip.hipEventDestroy(a)
             self.hip.hipEventDestroy(b)
-
-
-def _csv_rows(pattern):
-    import csv
-    import glob
-
-    rows = []
-    for f in sorted(glob.glob(pattern, recursive=True)):
-        with open(f) as fh:
-            rows.extend({k.lower(): v for k, v in r.items()} for r in csv.DictReader(fh))
-    return rows
-
-
-def summarize_profile(trace_dir: str, fetch_dir: str, write_dir: str, cmd_trace: str, cmd_fetch: str,
-                      cmd_write: str) -> None:
-    """Write the committed profile summaries from rocprofv3 CSV output (kernel stats and the
-    FETCH_SIZE / WRITE_SIZE counter runs)."""
-    import statistics
-
-    stats = _csv_rows(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
-    lines = ["# Kernel trace: SBM n=8,000,000, k=16, p=1.1, FP32, interleaved U|V", "",
-             "Command (from the repository root, on one MI355X):", "", "```", cmd_trace, "```", "",
-             "| kernel | calls | average us | share % |", "|---|---|---|---|"]
-    for r in stats[:14]:
-        name = r["name"].replace("pspec::(anonymous namespace)::", "")
-        name = name.split("(")[0][:80]
-        lines.append(f"| `{name}` | {r['calls']} | {float(r['averagens']) / 1e3:.1f} | {float(r['percentage']):.1f} |")
-    with open(os.path.join(PROFILES, "edge_hvp_sbm8m_kernel_trace.md"), "w") as f:
-        f.write("\n".join(lines) + "\n")
-
-    def per_dispatch(rows, counter, pred):
-        vals = [float(r["counter_value"]) for r in rows if r["counter_name"] == counter and pred(r["kernel_name"])]
-        return statistics.median(vals) if vals else None
-
-    fetch = _csv_rows(os.path.join(fetch_dir, "**", "*counter_collection.csv"))
-    write = _csv_rows(os.path.join(write_dir, "**", "*counter_collection.csv"))
-    is_edge = lambda nm: EDGE_KERNEL in nm.replace("pspec::(anonymous namespace)::", "")  # noqa: E731
-    is_copy = lambda nm: "axpby_k<float, 16, true>" in nm  # the calibration copy (bench.py --copy-calibration)
-    f_edge = per_dispatch(fetch, "FETCH_SIZE", is_edge)
-    w_edge = per_dispatch(write, "WRITE_SIZE", is_edge)
-    f_copy = per_dispatch(fetch, "FETCH_SIZE", is_copy)
-    w_copy = per_dispatch(write, "WRITE_SIZE", is_copy)
-    kib = COPY_BYTES / 1024.0
-    f_scale = kib / f_copy if f_copy else None
-    w_scale = kib / w_copy if w_copy else None
-    traffic = None
-    if f_edge is not None and w_edge is not None and f_scale and w_scale:
-        traffic = (f_edge * f_scale + w_edge * w_scale) * 1024.0
-    out = {
-        "workload": "sbm8m",
-        "layout": "interleaved",
-        "kernel": EDGE_KERNEL,
-        "source_hash": edge_source_hash(),
-        "fetch_kib_per_dispatch": f_edge,
-        "write_kib_per_dispatch": w_edge,
-        "copy_fetch_kib": f_copy,
-        "copy_write_kib": w_copy,
-        "fetch_scale": f_scale,
-        "write_scale": w_scale,
-        "bytes_per_launch": traffic,
-        "commands": [cmd_fetch, cmd_write],
-    }
-    with open(TRAFFIC_FILE, "w") as f:
-        json.dump(out, f, indent=1)
-    alg = None
-    md = ["# HBM traffic of the fused grad+HVP edge pass: SBM n=8,000,000, k=16, FP32", "",
-          "Counter runs (from the repository root, one MI355X, one counter block per run):", "", "```",
-          cmd_fetch, cmd_write, "```", "",
-          f"A plain device copy of {COPY_BYTES >> 20} MiB (read and written once) calibrates each counter: "
-          f"scale = known KiB / counted KiB.", "",
-          "| quantity | value |", "|---|---|",
-          f"| FETCH_SIZE, edge kernel (KiB/dispatch, median) | {f_edge} |",
-          f"| WRITE_SIZE, edge kernel (KiB/dispatch, median) | {w_edge} |",
-          f"| FETCH_SIZE, copy (KiB) | {f_copy} |", f"| WRITE_SIZE, copy (KiB) | {w_copy} |",
-          f"| fetch scale | {f_scale} |", f"| write scale | {w_scale} |",
-          f"| HBM bytes per launch (scaled) | {traffic} |"]
-    with open(os.path.join(PROFILES, "edge_hvp_sbm8m_traffic.md"), "w") as f:
-        f.write("\n".join(md) + "\n")
-    del alg
 
 
 def cpu_baseline(g, U_h, V_h, k: int, p: float, eps: float, workload: str):
@@ -315,18 +324,19 @@ def main() -> int:
                     help="skip the side measurements (per-call times, cold edge pass, streaming-read rate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
-    ap.add_argument("--summarize-valu", nargs=4, metavar=("PMC_DIR", "CMD", "NNZ", "K"),
-                    help="write the VALU counter summary of the edge kernel and exit")
-    ap.add_argument("--summarize-profile", nargs=6, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR", "CMD_TRACE",
-                                                            "CMD_FETCH", "CMD_WRITE"),
-                    help="write the profiles/ summaries from rocprofv3 CSV output and exit (no GPU needed)")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
+                    help="WORKLOAD NNZ K OUT_NAME DIR::COMMAND [DIR::COMMAND ...]: write profiles/OUT_NAME.md "
+                         "(and the traffic / VALU json of the edge pass) from rocprofv3 --pmc CSV output and exit")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "WORKLOAD", "COMMAND", "OUT_NAME"),
+                    help="write profiles/OUT_NAME.md from a rocprofv3 --kernel-trace --stats CSV run and exit")
     args = ap.parse_args()
-    if args.summarize_valu:
-        summarize_valu(args.summarize_valu[0], args.summarize_valu[1], int(args.summarize_valu[2]),
-                       int(args.summarize_valu[3]))
+    if args.summarize_pmc:
+        w, nnz, k, out_name, *runs = args.summarize_pmc
+        summarize_pmc(w, int(nnz), int(k), out_name, runs)
         return 0
-    if args.summarize_profile:
-        summarize_profile(*args.summarize_profile)
+    if args.summarize_trace:
+        d, w, cmd, out_name = args.summarize_trace
+        summarize_trace(d, w, cmd, out_name)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -418,7 +428,8 @@ def main() -> int:
 
     def extras(reps: int = 10):
         """FP32 side measurements (not the metric): each call of the step on its own, the unfused
-        pspec_hvp call (edge pass + epilogue), one k-means step on U's rows (k clusters) with its
+        pspec_hvp call (edge pass + epilogue), the fixed-U Riemannian Hessian of the truncated-CG loop
+        (pspec_rhess), the gather floor of the edge pass, one k-means step on U's rows (k clusters) with its
         algorithmic rate, the edge pass with the Infinity Cache flushed before every run, and a
         streaming-read reference rate of this GPU (pspec_dot over 2 GiB)."""
         dtype = torch.float32
@@ -434,6 +445,8 @@ def main() -> int:
         calls = {
             "rhvp": lambda: pspec.rhvp(dg, U, V, p, eps, RH=RH, RG=RG, MG=MG, F_col=Fc),
             "hvp": lambda: pspec.hvp(dg, U, V, p, eps, HV=HV, G=G, F_col=Fc),
+            # the truncated-CG call at a fixed U: G (the gradient at U) from the hvp call above
+            "rhess": lambda: pspec.rhess(dg, U, V, G, p, eps, RH=RH, MG=MG, F_col=Fc),
             "project": lambda: pspec.project(U, G, out=RG, M=MG),
             "retract": lambda: pspec.retract(U, RG, -1e-3, out=Un),
             "objective": lambda: pspec.objective(dg, Un, p, F_col=Fc, F=F),

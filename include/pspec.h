@@ -82,18 +82,31 @@ typedef struct ihipEvent_t *pspec_event;
 #define PSPEC_K_MAX 64
 
 /*
- * pspec_graph_workspace_bytes -- device workspace a graph handle needs (the state behind the
- * EucGrad / EucHessianEta callbacks of Section 2: row schedule, FP64 partial sums, per-column
- * scalars, partial rows of long rows).  A bound from the sizes alone, valid for every CSR with n
- * nodes and nnz stored entries: with h = min(n, nnz / (PSPEC_LIGHT_MAX + 1)) possible heavy rows
- * and s = min(n, nnz / (PSPEC_CHUNK + 1)) possible split rows it is about
- *   24 (nnz / PSPEC_CHUNK + h) + 16 s + 16 k_max (nnz / PSPEC_CHUNK + s)
- *   + 32 k_max (n / 256 + 2048) + 8240 k_max + 32 n / 256        bytes
- * (SBM n = 8M, nnz = 96M, k_max = 16: ~190 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32: ~380 MB).
- * Returns 0 for arguments pspec_graph_create would reject (n < 1, nnz < 0, k_max outside
- * 1..PSPEC_K_MAX, n >= 2^31 - 1).
+ * Graph workspace.  A graph handle keeps its state (the state behind the EucGrad / EucHessianEta
+ * callbacks of Section 2: row schedule, FP64 partial sums, per-column scalars, partial rows of long
+ * rows) in device memory the caller provides.  Two ways to size it:
+ *
+ * pspec_graph_workspace_bytes -- a bound from the sizes alone, enough for every CSR with n nodes
+ *   and nnz stored entries.  With h = min(n, nnz / (PSPEC_LIGHT_MAX + 1)) possible heavy rows,
+ *   s = min(n, nnz / (PSPEC_CHUNK + 1)) possible split rows and c = nnz / PSPEC_CHUNK + 8 s possible
+ *   chunks of split rows, it is about
+ *     24 (h + c) + 16 s + 16 k_max c + 32 k_max (n / 256 + 2048) + 8240 k_max + 96 n / 256   bytes
+ *   (SBM n = 8M, nnz = 96M, k_max = 16: ~560 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32: ~1.3 GB).
+ *   Returns 0 for arguments pspec_graph_create would reject (n < 1, nnz < 0, k_max outside
+ *   1..PSPEC_K_MAX, n >= 2^31 - 1).
+ *
+ * pspec_graph_exact_workspace -- the exact size for one graph: validates the CSR and counts its
+ *   schedule in `workspace` (device, 256-byte aligned, at least
+ *   pspec_graph_count_workspace_bytes(n, k_max) bytes: the counters and partial sums, which depend
+ *   on n and k_max only), writes the bytes pspec_graph_create needs for this graph to *needed (a
+ *   host size_t) and synchronises `stream` once.  The same workspace, grown to *needed bytes, can
+ *   then be passed to pspec_graph_create (SBM n = 8M, k_max = 16: ~23 MB; R-MAT-22, k_max = 32:
+ *   ~210 MB).  Arguments and errors as for pspec_graph_create.
  */
 size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max);
+size_t pspec_graph_count_workspace_bytes(int64_t n, int k_max);
+pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col, int k_max,
+                                         void *workspace, size_t ws_bytes, pspec_stream stream, size_t *needed);
 
 /*
  * pspec_graph_create -- build the row schedule of a graph (degree binning) in caller memory.
@@ -103,16 +116,21 @@ size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max);
  *   wtype           element type of w.  F32 calls need PSPEC_F32 weights; F64 calls accept
  *                   either (FP32 weights are promoted exactly).
  *   k_max           largest k any later call on this handle will use (1..PSPEC_K_MAX).
- *   workspace       device memory of ws_bytes >= pspec_graph_workspace_bytes(n, nnz, k_max) bytes,
+ *   workspace       device memory of ws_bytes >= pspec_graph_workspace_bytes(n, nnz, k_max) bytes
+ *                   (or at least the exact size pspec_graph_exact_workspace reports for this graph),
  *                   256-byte aligned, owned by the caller and BORROWED like the CSR (a smaller one
  *                   returns PSPEC_ERR_WORKSPACE).  Its contents need no initialisation.
  *   stream          the schedule is built on this stream; the call synchronises it once to read
  *                   back the sizes of the schedule.
  *   out             receives the handle (a small host object).
  * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
- * 16-lane group per row in node order; longer rows are cut into chunks of at most PSPEC_CHUNK
- * edges, handed out in a fixed order to one wavefront each, and rows spanning several chunks are
- * combined in a fixed order afterwards, so every result is bit-reproducible.  The CSR is
+ * 16-lane group per row in node order; rows of up to PSPEC_CHUNK edges are one chunk each, handed
+ * out in a fixed order to one wavefront each; longer rows are cut at 8 column-segment boundaries
+ * (node-id ranges holding equal shares of the stored entries) and each piece into chunks of at
+ * most PSPEC_CHUNK edges, the chunks of segment s going to the workgroups that run on XCD s, and
+ * such rows are combined in a fixed order afterwards, so every result is bit-reproducible.  Any
+ * column order within a row is valid; ascending columns (the usual CSR) let each XCD's L2 cache
+ * the neighbour rows of one segment only.  The CSR is
  * validated on the device (rowptr monotone with rowptr[0] = 0 and rowptr[n] = nnz, every column
  * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  No device memory is allocated.
  */
@@ -263,6 +281,24 @@ pspec_status pspec_retract(int64_t n, int k, pspec_dtype dt, const void *U, int6
 pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
                         int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
                         double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream);
+
+/*
+ * pspec_rhess -- the Riemannian Hessian-vector product of pspec_rhvp at a point U whose Euclidean
+ * gradient G is already known: the form truncated CG needs, since U stays fixed while the Hessian is
+ * applied to one direction after another within a Newton step (Section 2):
+ *   RH = HV - U (U^T HV) - V MG,   MG = U^T G   (MG written if not NULL)
+ * with HV the exact Hessian-vector product of pspec_hvp.  G (n x k, dt, leading dimension ldg) is
+ * the Euclidean gradient at U as pspec_grad or pspec_hvp returns it; it is only read.  Compared
+ * with pspec_rhvp the edge pass forms no (Delta_p u) rows and writes none, g^T v is summed from G
+ * directly, and RG is not formed or written: one n x k row block less written per call on each side
+ * (SBM n = 8M, k = 16: 1 GB of the ~20 GB a pspec_rhvp call moves).  RH agrees with pspec_rhvp's
+ * to rounding (b = g^T v is summed from the rounded G instead of from (Delta_p u)^T v), F_col and MG
+ * bit for bit.  V, RH, ws, F_col, layout and errors as for pspec_rhvp; RH must not overlap U, V or
+ * G.
+ */
+pspec_status pspec_rhess(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                         int64_t ldv, const void *G, int64_t ldg, double p, double eps, void *RH, int64_t ldrh,
+                         double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream);
 
 /*
  * pspec_rhvp_static -- pspec_rhvp for callers that cannot allocate device memory (code under HIP

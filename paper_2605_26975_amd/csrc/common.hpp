@@ -39,10 +39,13 @@ void clear_error();
     } while (0)
 
 // ---- row schedule ----------------------------------------------------------------------------
-// A heavy row (degree > PSPEC_LIGHT_MAX) is cut into chunks of at most PSPEC_CHUNK edges.  A chunk
-// whose row has a single chunk writes the row's results directly (slot = -1); otherwise it writes
-// partial rows into scratch slot `slot` (its rank among the chunks of such rows) and the row is
-// combined afterwards from slots first .. first + count - 1 (Split).
+// A heavy row (degree > PSPEC_LIGHT_MAX) of at most PSPEC_CHUNK edges is one chunk of the shared list
+// and writes its results directly (slot = -1).  A longer (split) row is cut by column segment (kSegs
+// ranges of node ids holding equal shares of the stored entries) and each piece into chunks of at
+// most PSPEC_CHUNK edges; the chunks of segment s are processed by the workgroups with
+// blockIdx.x % kSegs == s, which the dispatcher places on one XCD, so each XCD's L2 caches the rows of
+// one segment only.  Such chunks write partial rows into scratch slot `slot` and the row is combined
+// afterwards from slots first .. first + count - 1 (Split).
 struct Chunk {
     int64_t beg, end;
     int32_t row, slot;
@@ -51,6 +54,7 @@ struct Split {
     int32_t row, first, count, pad;
 };
 
+constexpr int kSegs = 8;           // column segments of split rows: the XCDs of an MI355X
 constexpr int kBlock = 256;        // threads per workgroup of every kernel here
 constexpr int kHeavyPerCUMax = 8;  // most resident workgroups per CU of the persistent heavy-chunk kernel
 constexpr int kHeavyGridCap = 2048;  // most workgroups of the heavy-chunk kernel (8 per CU on 256 CUs)
@@ -72,6 +76,8 @@ struct Graph {
     int device = 0;
     int64_t tiles = 0;         // light tiles = ceil(n / kTileRows)
     int64_t heavy_rows = 0, n_chunks = 0, n_split = 0, n_split_chunks = 0;
+    int64_t seg_chunk_base[kSegs + 1] = {};  // chunks of segment s: [seg_chunk_base[s], seg_chunk_base[s + 1]);
+                                             // the shared list follows, up to n_chunks
     int64_t heavy_grid_max = 0;  // most workgroups of the heavy-chunk kernel (one partial row each)
     int cus = 1;                 // compute units of the device
     Chunk *chunks = nullptr;   // device [n_chunks]

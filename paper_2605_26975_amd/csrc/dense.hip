@@ -3,13 +3,13 @@
 // product / axpby used by the truncated-CG driver.
 //
 // Every sum over the n rows is FP64 and deterministic: a fixed grid of kDenseBlocks workgroups, each
-// owning a contiguous row range, writes one partial, and a single workgroup adds the partials in
-// order.  Gram: each thread owns a 4 x 4 block of the k x k result and streams the rows of its
-// workgroup's range through LDS (the FP64 VALU work, 2 k^2 flops per row, stays below the HBM time of
-// reading the two n x k inputs for k <= 32; FP64 matrix cores run at the same rate as the FP64 VALU
-// on this GPU, so they would not shorten it).  Apply, dot and axpby: one lane per row, the row moved
-// with 16-byte loads and stores; the k x k matrices of apply are read at wave-uniform addresses, so
-// they come through the scalar cache into SGPR operands of the FMAs instead of through LDS.
+// owning a contiguous row range, writes one partial, and the partials are added by a fixed two-level
+// tree.  Gram matrices (k > 4) and the row-block products X M of the projection and retraction run on
+// the FP64 matrix cores (v_mfma_f64_16x16x4f64, four rows per instruction; dense.hpp), which keeps
+// them below the HBM time of their passes at k = 32, where the FP64 VALU was bound by operand
+// delivery; for k <= 4 each lane accumulates its rows' k x k products by FP64 FMA and the wave adds
+// them by DPP (a 16-column matrix tile would leave three quarters of its lanes idle).  Dot and axpby:
+// one lane per row, the row moved with 16-byte loads and stores.
 #include <cmath>
 
 #include "common.hpp"

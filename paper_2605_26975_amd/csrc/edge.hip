@@ -28,7 +28,12 @@
 namespace pspec {
 namespace {
 
-enum Mode { OBJ = 0, GRAD = 1, HVP = 2 };
+// OBJ: N and D only.  GRAD: also L = Delta_p u.  HVP: also J (needs V) and the scalars of the
+// rank-2 term.  HESS: the Hessian at a fixed U whose gradient G is given: J and the rank-2 scalars,
+// with b = g^T v summed from G, no L.
+enum Mode { OBJ = 0, GRAD = 1, HVP = 2, HESS = 3 };
+constexpr bool mode_l(int m) { return m == GRAD || m == HVP; }  // forms L
+constexpr bool mode_v(int m) { return m == HVP || m == HESS; }  // reads V, forms J
 
 // |x|^(p-2) for x >= 0.  FP32: hardware exp2/log2 on max(x, 2^-64), so an exact zero gives a finite
 // value (2^(64 (2-p))) whose product with x is exactly 0.  FP64: exp(q ln x) for x clamped to
@@ -117,7 +122,9 @@ struct EdgeArgs {
     int k;
     const T *U;
     const T *V;
+    const T *Gc;                              // HESS: the gradient at U (n x k), else NULL
     uint32_t ldu_b, ldv_b, U_bytes, V_bytes;  // leading dimensions and extents in bytes
+    uint32_t ldg_b, G_bytes;
     T *L;                                     // raw (Delta_p u) rows  (the G output)
     T *J;                                     // raw Hessian edge rows (the HV output)
     int64_t ldl, ldj;
@@ -126,9 +133,11 @@ struct EdgeArgs {
     int light_max;
     double *partials;  // [(tiles + heavy workgroups)][kQ][k]
     const Chunk *chunks;
-    double *scratch;   // [chunks][2][k_max]
+    double *scratch;   // [split chunks][2][k_max]
     int k_max;
     int64_t part_base; // first partial row of the chunks (= tiles)
+    int64_t seg_base[kSegs + 1];  // chunks of column segment s: [seg_base[s], seg_base[s + 1])
+    int64_t n_chunks;             // the shared list: [seg_base[kSegs], n_chunks)
 };
 
 // One edge-column term.  wv is the weight (0 for padding lanes, whose gather is the row itself).
@@ -149,8 +158,8 @@ struct Term {
         const T wh = wv * h;
         const T wphi = wh * x;  // w phi_p(x)
         Ns = fma(wphi, x, Ns);  // w |x|^p
-        if (MODE != OBJ) Ls += wphi;
-        if (MODE == HVP) {
+        if (mode_l(MODE)) Ls += wphi;
+        if (mode_v(MODE)) {
             const T wpsi = fmin(wh, wv * epsc);  // w psi(x)
             Js = fma(wpsi, vi - vj, Js);
         }
@@ -259,6 +268,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
 
     const auto rU = make_rsrc(a.U, a.U_bytes);
     const auto rV = make_rsrc(a.V, a.V_bytes);
+    const auto rG = make_rsrc(a.Gc, a.G_bytes);
     // What row rl needs before its gathers: own u_i, v_i, and the first chunk's neighbour offsets
     // (padding: the row itself, weight 0).  Loaded one row ahead.
     struct RowPre {
@@ -274,7 +284,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
 #pragma unroll
         for (int m = 0; m < CPL; ++m) {
             r.ui[m] = bload<T>(rU, j * a.ldu_b + cb[m]);
-            r.vi[m] = (MODE == HVP) ? bload<T>(rV, j * a.ldv_b + cb[m]) : (T)0;
+            r.vi[m] = mode_v(MODE) ? bload<T>(rV, j * a.ldv_b + cb[m]) : (T)0;
         }
         r.wl = (T)0;
         if (valid) {
@@ -335,11 +345,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                 }
                 if (u * EPR < cnt) {
                     const uint32_t bu = (uint32_t)edge_bcast<G, EPR, u>((int32_t)ou, e, lane);
-                    const uint32_t bv = (MODE == HVP) ? (uint32_t)edge_bcast<G, EPR, u>((int32_t)ov, e, lane) : 0u;
+                    const uint32_t bv = mode_v(MODE) ? (uint32_t)edge_bcast<G, EPR, u>((int32_t)ov, e, lane) : 0u;
 #pragma unroll
                     for (int m = 0; m < CPL; ++m) {
                         uj[u][m] = bload<T>(rU, bu + cb[m]);
-                        if (MODE == HVP) vj[u][m] = bload<T>(rV, bv + cb[m]);
+                        if (mode_v(MODE)) vj[u][m] = bload<T>(rV, bv + cb[m]);
                     }
                 }
             });
@@ -363,8 +373,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
             if (EPR > 1) {
 #pragma unroll
                 for (int o = KL; o < G; o <<= 1) {
-                    if (MODE != OBJ) Ls[m] += __shfl_xor(Ls[m], o);
-                    if (MODE == HVP) Js[m] += __shfl_xor(Js[m], o);
+                    if (mode_l(MODE)) Ls[m] += __shfl_xor(Ls[m], o);
+                    if (mode_v(MODE)) Js[m] += __shfl_xor(Js[m], o);
                 }
             }
             q[0][m] += (double)Ns[m];
@@ -373,14 +383,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                 const T hi = a.pw(fabs(ui));
                 const T phi = hi * ui;  // phi_p(u_i)
                 q[1][m] += (double)(phi * ui);
-                if (MODE == HVP) {
-                    q[2][m] += (double)phi * (double)vi;
-                    if (light) q[3][m] += (double)Ls[m] * (double)vi;
+                if (mode_v(MODE)) q[2][m] += (double)phi * (double)vi;
+                if (MODE == HVP && light) q[3][m] += (double)Ls[m] * (double)vi;
+                if (MODE == HESS) {  // g^T v over every row, g_i read here (not held through the row)
+                    const T gi = bload<T>(rG, (uint32_t)row * a.ldg_b + cb[m]);
+                    q[3][m] += (double)gi * (double)vi;
                 }
                 const int cm = c + m * KL;
                 if (light && cm < a.k) {
-                    if (MODE != OBJ) a.L[row * a.ldl + cm] = Ls[m];
-                    if (MODE == HVP) a.J[row * a.ldj + cm] = Js[m];
+                    if (mode_l(MODE)) a.L[row * a.ldl + cm] = Ls[m];
+                    if (mode_v(MODE)) a.J[row * a.ldj + cm] = Js[m];
                 }
             }
         }
@@ -409,8 +421,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     }
 }
 
-// Heavy rows: chunks of at most PSPEC_CHUNK edges handed out in a fixed order to persistent waves
-// (wave W of the grid takes chunks W, W + NW, W + 2 NW, ...).  A wave stages its chunk's neighbour
+// Heavy rows: chunks of at most PSPEC_CHUNK edges handed out in a fixed order to persistent waves.
+// Workgroup b first serves column segment s = b % kSegs (the XCD it runs on): its waves take that
+// segment's chunks in turn, so one XCD's L2 only ever holds neighbour rows of one segment; then every
+// wave W of the grid takes the shared list's chunks W, W + NW, W + 2 NW, ...  A wave stages its chunk's neighbour
 // byte offsets and weights in its own slice of LDS (no workgroup barrier), runs ES = 64 / K edge
 // slots of K column lanes with UNR gathers in flight per lane (slots past the chunk gather the row
 // itself with weight 0, so every load is unconditional), adds the slots up with cross-lane sums,
@@ -418,7 +432,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
 // FP64 column sums of w |x|^p and L_i v_i from chunk to chunk.  Each workgroup writes one partial
 // row, its waves added in order, so the result does not depend on timing.
 template <typename T, typename WT, int K, int MODE, int UNR, bool FLOOR = false>
-__global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t n_chunks) {
+__global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
     constexpr int KW = K < 64 ? K : 64;  // column lanes of an edge slot
     constexpr int ES = 64 / KW;          // edge slots per wave
     constexpr int NWB = kBlock / 64;     // waves per workgroup
@@ -432,8 +446,7 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
     const auto rU = make_rsrc(a.U, a.U_bytes);
     const auto rV = make_rsrc(a.V, a.V_bytes);
     double Nacc = 0.0, Sacc = 0.0;
-    const int64_t NW = (int64_t)gridDim.x * NWB;
-    for (int64_t ci = (int64_t)blockIdx.x * NWB + wv; ci < n_chunks; ci += NW) {
+    auto chunk = [&](int64_t ci) {
         const Chunk ch = a.chunks[ci];
         const int len = (int)(ch.end - ch.beg);
         for (int t0 = 0; t0 < len; t0 += 4 * 64) {  // four ids per lane in flight
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
         const uint32_t row = (uint32_t)ch.row;
         const uint32_t own_u = row * a.ldu_b + cb, own_v = row * a.ldv_b + cb;
         const T ui = bload<T>(rU, own_u);
-        const T vi = MODE == HVP ? bload<T>(rV, own_v) : T(0);
+        const T vi = mode_v(MODE) ? bload<T>(rV, own_v) : T(0);
         T Ls = 0, Js = 0, Ns = 0;
         for (int base = 0; base < len; base += ES * UNR) {
             // all staged offsets of the batch are read before any is used (see pin)
@@ -478,13 +491,13 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
                 const int idx = base + u * ES + e;
                 const int ix = idx < len ? idx : 0;
                 ou[u] = s_ou[wv][ix];
-                if (MODE == HVP) ov[u] = s_ov[wv][ix];
+                if (mode_v(MODE)) ov[u] = s_ov[wv][ix];
                 wt[u] = s_w[wv][ix];
             }
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 pin(ou[u]);
-                if (MODE == HVP) pin(ov[u]);
+                if (mode_v(MODE)) pin(ov[u]);
                 pin(wt[u]);
             }
 #pragma unroll
@@ -492,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
                 const bool ok = base + u * ES + e < len;
                 wt[u] = ok ? wt[u] : T(0);
                 uj[u] = bload<T>(rU, ok ? ou[u] + cb : own_u);
-                if (MODE == HVP) vj[u] = bload<T>(rV, ok ? ov[u] + cb : own_v);
+                if (mode_v(MODE)) vj[u] = bload<T>(rV, ok ? ov[u] + cb : own_v);
                 else vj[u] = T(0);
             }
 #pragma unroll
@@ -503,13 +516,13 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
 #pragma unroll
         for (int o = KW; o < 64; o <<= 1) {
             L += __shfl_xor(L, o);
-            if (MODE == HVP) J += __shfl_xor(J, o);
+            if (mode_v(MODE)) J += __shfl_xor(J, o);
             N += __shfl_xor(N, o);
         }
         if (e == 0 && c < a.k) {
             if (ch.slot < 0) {
-                if (MODE != OBJ) a.L[(int64_t)row * a.ldl + c] = (T)L;
-                if (MODE == HVP) a.J[(int64_t)row * a.ldj + c] = (T)J;
+                if (mode_l(MODE)) a.L[(int64_t)row * a.ldl + c] = (T)L;
+                if (mode_v(MODE)) a.J[(int64_t)row * a.ldj + c] = (T)J;
             } else {
                 a.scratch[((int64_t)ch.slot * 2 + 0) * a.k_max + c] = L;
                 a.scratch[((int64_t)ch.slot * 2 + 1) * a.k_max + c] = J;
@@ -521,7 +534,15 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a, int64_t 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    {  // this workgroup's column segment (gridDim.x is a multiple of kSegs)
+        const int sg = blockIdx.x % kSegs;
+        const int64_t step = (int64_t)(gridDim.x / kSegs) * NWB;
+        for (int64_t ci = a.seg_base[sg] + (int64_t)(blockIdx.x / kSegs) * NWB + wv; ci < a.seg_base[sg + 1]; ci += step)
+            chunk(ci);
     }
+    const int64_t NW = (int64_t)gridDim.x * NWB;
+    for (int64_t ci = a.seg_base[kSegs] + (int64_t)blockIdx.x * NWB + wv; ci < a.n_chunks; ci += NW) chunk(ci);
     if (e == 0) {
         s_acc[wv][0][c] = Nacc;
         s_acc[wv][1][c] = Sacc;
@@ -558,8 +579,8 @@ __global__ __launch_bounds__(kBlock) void combine_split(const Split *__restrict_
         Ls += scratch[((int64_t)(sp.first + q) * 2 + 0) * k_max + c];
         Js += scratch[((int64_t)(sp.first + q) * 2 + 1) * k_max + c];
     }
-    L[(int64_t)sp.row * ldl + c] = (T)Ls;
-    if (MODE == HVP) J[(int64_t)sp.row * ldj + c] = (T)Js;
+    if (mode_l(MODE)) L[(int64_t)sp.row * ldl + c] = (T)Ls;
+    if (mode_v(MODE)) J[(int64_t)sp.row * ldj + c] = (T)Js;
 }
 
 // Stage 1: workgroup b sums a contiguous range of partial rows, R rows in parallel per quantity.
@@ -587,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void reduce_stage1(const double *__restrict
 // Stage 2 (one workgroup): totals and the per-column scalars.
 __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict__ red1, int W, int k, double p,
                                                       double *__restrict__ sc, int k_max, double *__restrict__ F_col,
-                                                      double *__restrict__ F, bool rank2) {
+                                                      double *__restrict__ F, bool rank2, bool b_direct) {
     __shared__ double s[kBlock];
     __shared__ double sf[PSPEC_K_MAX];
     const int tid = threadIdx.x;
@@ -606,7 +627,8 @@ __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict
         sc[SC_PD * k_max + tid] = pD;
         // without the rank-2 part of the Hessian the epilogue's g a + phi b term is zero
         sc[SC_A * k_max + tid] = rank2 ? av : 0.0;
-        sc[SC_B * k_max + tid] = rank2 ? pD * (S - Fl * av) : 0.0;
+        // b = g^T v: from L^T v (HVP) or summed from the given gradient (HESS)
+        sc[SC_B * k_max + tid] = rank2 ? (b_direct ? S : pD * (S - Fl * av)) : 0.0;
         sf[tid] = Fl;
         if (F_col) F_col[tid] = Fl;
     }
@@ -630,16 +652,17 @@ __device__ __forceinline__ ColScalars col_scalars(const double *__restrict__ sc,
 // Hessian over p - 1), the gradient g = (p/D)(L - F phi_p(u)) and
 // HV = (p/D)((p-1) J - F (p-1) psi(u) v - g a - phi_p(u) b), both rounded to T.  Every kernel that
 // forms these entries goes through this function, so they agree bit for bit; contraction into
-// FMAs is off here, since the compiler would otherwise fuse differently in different kernels.
+// FMAs is off here, since the compiler would otherwise fuse differently in different kernels.  In
+// HESS mode l is the given gradient g itself (U fixed), and only HV is formed.
 template <typename T, int MODE>
 __device__ __forceinline__ void epilogue(const PowM2<T> &pw, T epsc, double p, const ColScalars &s, T u, T v, T l,
                                          T j, T &gout, T &hout) {
 #pragma clang fp contract(off)
     const T h = pw(fabs(u));
     const T phi = h * u;
-    const double g = s.pD * ((double)l - s.F * (double)phi);
+    const double g = MODE == HESS ? (double)l : s.pD * ((double)l - s.F * (double)phi);
     gout = (T)g;
-    if (MODE == HVP) {
+    if (mode_v(MODE)) {
         const T psi = fmin(h, epsc);
         const double hv = s.pD * ((p - 1.0) * (double)j - s.F * (p - 1.0) * (double)psi * (double)v - g * s.a -
                                   (double)phi * s.b);
@@ -658,12 +681,12 @@ __global__ __launch_bounds__(kBlock) void finalize(int64_t n, int k, const T *__
     if (c >= k) return;
     const ColScalars cs = col_scalars(sc, k_max, c);
     for (int64_t i = (int64_t)blockIdx.x * (kBlock / K) + threadIdx.x / K; i < n; i += stride) {
-        const T v = MODE == HVP ? V[i * ldv + c] : T(0);
-        const T j = MODE == HVP ? HV[i * ldh + c] : T(0);
+        const T v = mode_v(MODE) ? V[i * ldv + c] : T(0);
+        const T j = mode_v(MODE) ? HV[i * ldh + c] : T(0);
         T g, hv;
         epilogue<T, MODE>(pw, epsc, p, cs, U[i * ldu + c], v, G[i * ldg + c], j, g, hv);
-        G[i * ldg + c] = g;
-        if (MODE == HVP) HV[i * ldh + c] = hv;
+        if (MODE != HESS) G[i * ldg + c] = g;  // in HESS mode G is the given gradient, read only
+        if (mode_v(MODE)) HV[i * ldh + c] = hv;
     }
 }
 
@@ -671,8 +694,9 @@ __global__ __launch_bounds__(kBlock) void finalize(int64_t n, int k, const T *__
 // grid of kDenseBlocks, each over a contiguous row range) the FP64 partials of U^T G and U^T HV on
 // the matrix cores, with G and HV formed from the raw rows L, J by the epilogue above and never
 // stored.  Rows, groups and the MFMA sequence are those of the stand-alone Gram kernel, so the sums
-// equal the Gram matrices of the finalized G and HV bit for bit.
-template <typename T, int K>
+// equal the Gram matrices of the finalized G and HV bit for bit.  In HESS mode L is the given
+// gradient.
+template <typename T, int K, int MODE = HVP>
 __global__ __launch_bounds__(kBlock) void finalize_gram(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
                                                       const T *__restrict__ V, int64_t ldv, const T *__restrict__ L,
                                                       int64_t ldl, const T *__restrict__ J, int64_t ldj, PowM2<T> pw,
@@ -718,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void finalize_gram(int64_t n, int k, const 
         for (int t = 0; t < CT; ++t) {
             const bool ok = row < r1 && 16 * t + cl < k;
             T g, hv;
-            epilogue<T, HVP>(pw, epsc, p, cs[t], raw.u[t], raw.v[t], raw.l[t], raw.j[t], g, hv);
+            epilogue<T, MODE>(pw, epsc, p, cs[t], raw.u[t], raw.v[t], raw.l[t], raw.j[t], g, hv);
             a[t] = ok ? raw.u[t] : T(0);
             b[0][t] = ok ? g : T(0);
             b[1][t] = ok ? hv : T(0);
@@ -732,8 +756,9 @@ __global__ __launch_bounds__(kBlock) void finalize_gram(int64_t n, int k, const 
 //   RG = G - U MG,   RH = HV - U MH - V MG,   MG = U^T G, MH = U^T HV,
 // with G and HV formed again from the raw rows (held in RG and RH on entry, overwritten in place) by
 // the shared epilogue.  The products follow the MFMA sequence of the stand-alone projection (U then
-// V, each in k order), so the outputs equal pspec_project's bit for bit.
-template <typename T, int K, bool VEC>
+// V, each in k order), so the outputs equal pspec_project's bit for bit.  In HESS mode RG holds the
+// given gradient (read only) and only RH is written.
+template <typename T, int K, bool VEC, int MODE = HVP>
 __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *__restrict__ U, int64_t ldu,
                                                    const T *__restrict__ V, int64_t ldv, T *__restrict__ RG,
                                                    int64_t ldrg, T *__restrict__ RH, int64_t ldrh, PowM2<T> pw, T epsc,
@@ -788,19 +813,21 @@ __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *
             mask_mf_chunk<T, K>(row0 + c, n, k, ua[s]);
             mask_mf_chunk<T, K>(row0 + c, n, k, va[s]);
             dbl4 acc[CT];
+            if constexpr (MODE == HVP) {
 #pragma unroll
-            for (int t = 0; t < CT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-            mf_products<T, K>(ua[s], -1.0, mg, acc);
+                for (int t = 0; t < CT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+                mf_products<T, K>(ua[s], -1.0, mg, acc);
 #pragma unroll
-            for (int t = 0; t < CT; ++t)
+                for (int t = 0; t < CT; ++t)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t r = row0 + 4 * i + q;
-                    const int col = 16 * t + c;
-                    T g, hv;
-                    epilogue<T, GRAD>(pw, epsc, p, cs[t], u[s][t][i], v[s][t][i], l[s][t][i], j[s][t][i], g, hv);
-                    if (r < n && col < k) RG[r * ldrg + col] = (T)fma(1.0, (double)g, acc[t][i]);
-                }
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t r = row0 + 4 * i + q;
+                        const int col = 16 * t + c;
+                        T g, hv;
+                        epilogue<T, GRAD>(pw, epsc, p, cs[t], u[s][t][i], v[s][t][i], l[s][t][i], j[s][t][i], g, hv);
+                        if (r < n && col < k) RG[r * ldrg + col] = (T)fma(1.0, (double)g, acc[t][i]);
+                    }
+            }
 #pragma unroll
             for (int t = 0; t < CT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
             mf_products<T, K>(ua[s], -1.0, mh, acc);
@@ -812,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *
                     const int64_t r = row0 + 4 * i + q;
                     const int col = 16 * t + c;
                     T g, hv;
-                    epilogue<T, HVP>(pw, epsc, p, cs[t], u[s][t][i], v[s][t][i], l[s][t][i], j[s][t][i], g, hv);
+                    epilogue<T, MODE>(pw, epsc, p, cs[t], u[s][t][i], v[s][t][i], l[s][t][i], j[s][t][i], g, hv);
                     if (r < n && col < k) RH[r * ldrh + col] = (T)fma(1.0, (double)hv, acc[t][i]);
                 }
         }
@@ -842,9 +869,12 @@ int64_t heavy_grid(const Graph *g) {
             v = 1;
         per_cu = v < kHeavyPerCUMax ? v : kHeavyPerCUMax;
     }
+    if (g->n_chunks == 0) return 0;
     const int64_t want = (g->n_chunks + 3) / 4, cap = (int64_t)per_cu * g->cus;
-    const int64_t grid = want < cap ? want : cap;
-    return grid < g->heavy_grid_max ? grid : g->heavy_grid_max;  // the partial rows the workspace holds
+    int64_t grid = want < cap ? want : cap;
+    grid = grid < g->heavy_grid_max ? grid : g->heavy_grid_max;  // the partial rows the workspace holds
+    grid = grid / kSegs * kSegs;                                 // every segment served alike
+    return grid > kSegs ? grid : kSegs;
 }
 
 unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
@@ -857,7 +887,8 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
 // scalars; L and J receive the raw rows.
 template <typename T, typename WT, int K, int MODE, bool FLOOR = false>
 pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J, int64_t ldj,
-               double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2 = true) {
+               double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2 = true,
+               const T *Gc = nullptr, int64_t ldgc = 0) {
     EdgeArgs<T, WT> a;
     a.rowptr = g->rowptr;
     a.col = g->col;
@@ -870,6 +901,9 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.ldv_b = (uint32_t)(ldv * (int64_t)sizeof(T));
     a.U_bytes = (uint32_t)block_extent(g->n, k, ldu, sizeof(T));
     a.V_bytes = V ? (uint32_t)block_extent(g->n, k, ldv, sizeof(T)) : 0u;
+    a.Gc = Gc;
+    a.ldg_b = (uint32_t)(ldgc * (int64_t)sizeof(T));
+    a.G_bytes = Gc ? (uint32_t)block_extent(g->n, k, ldgc, sizeof(T)) : 0u;
     a.L = L;
     a.J = J;
     a.ldl = ldl;
@@ -882,18 +916,19 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.scratch = g->chunk_scratch;
     a.k_max = g->k_max;
     a.part_base = g->tiles;
+    for (int sg = 0; sg <= kSegs; ++sg) a.seg_base[sg] = g->seg_chunk_base[sg];
+    a.n_chunks = g->n_chunks;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
     edge_light<T, WT, K, MODE, FLOOR><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     const int64_t hb = heavy_grid<T, WT, K>(g);
-    if (hb > 0)
-        edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>(), FLOOR><<<(unsigned)hb, kBlock, 0, s>>>(a, g->n_chunks);
+    if (hb > 0) edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>(), FLOOR><<<(unsigned)hb, kBlock, 0, s>>>(a);
     if (g->n_split > 0 && MODE != OBJ)
         combine_split<T, MODE><<<grid_for(g->n_split * k, kBlock, 1 << 30), kBlock, 0, s>>>(
             g->splits, g->n_split, g->chunk_scratch, k, g->k_max, L, ldl, J, ldj);
     if (g->ev_after) PSPEC_HIP(hipEventRecord(g->ev_after, s));
     const int W = kQ * k;
     reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + hb, W, g->red1);
-    reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F, rank2);
+    reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F, rank2, MODE == HESS);
     return PSPEC_OK;
 }
 
@@ -924,7 +959,9 @@ constexpr bool rhvp_fused() {
 
 // Riemannian gradient and Hessian-vector product on Gr(k, n).  Workspace: level-1 partials
 // [kDenseBlocks][2][k*k], level-2 partials, then MG = U^T G and MH = U^T HV (k*k each).
-template <typename T, typename WT, int K, bool VEC>
+// MODE = HVP: RG and RH from U and V.  MODE = HESS: RH only, at a U whose Euclidean gradient is given
+// in RG (read only): the edge pass forms no L, and b = g^T v comes from the given gradient.
+template <typename T, typename WT, int K, bool VEC, int MODE = HVP>
 pspec_status launch_rhvp(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, double p, double eps, T *RH,
                  int64_t ldrh, T *RG, int64_t ldrg, double *MG_out, double *F_col, double *ws, hipStream_t s) {
     const int64_t n = g->n;
@@ -935,27 +972,31 @@ pspec_status launch_rhvp(Graph *g, int k, const T *U, int64_t ldu, const T *V, i
     PowM2<T> pw;
     pw.pm2 = (T)(p - 2.0);
     const T epsc = (T)std::pow(eps, p - 2.0);
-    const pspec_status st = edge_pass<T, WT, K, HVP>(g, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, p, eps, F_col, nullptr, s);
+    const pspec_status st =
+        MODE == HESS ? edge_pass<T, WT, K, HESS>(g, k, U, ldu, V, ldv, nullptr, 0, RH, ldrh, p, eps, F_col, nullptr, s,
+                                                 true, RG, ldrg)
+                     : edge_pass<T, WT, K, HVP>(g, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, p, eps, F_col, nullptr, s);
     if (st != PSPEC_OK) return st;
     if constexpr (rhvp_fused<T, K>()) {
-        finalize_gram<T, K><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc, p,
-                                                            g->scalars, g->k_max, part);
+        finalize_gram<T, K, MODE><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc,
+                                                                  p, g->scalars, g->k_max, part);
         sum_partials(part, (int)kk, mid, Mw, MG_out, s, 2 * (int64_t)kk);
         sum_partials(part + kk, (int)kk, mid, Mw + kk, nullptr, s, 2 * (int64_t)kk);
-        apply_rhvp<T, K, VEC><<<mf_grid(n), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc, p,
-                                                            g->scalars, g->k_max, Mw, Mw + kk);
+        apply_rhvp<T, K, VEC, MODE><<<mf_grid(n), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc,
+                                                                  p, g->scalars, g->k_max, Mw, Mw + kk);
     } else {  // wide rows: finalize, then the two projections with the stand-alone kernels, in place
-        finalize<T, K, HVP><<<grid_for(n, kBlock / K, 65536), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH,
-                                                                               ldrh, pw, epsc, p, g->scalars,
-                                                                               g->k_max);
+        finalize<T, K, MODE><<<grid_for(n, kBlock / K, 65536), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH,
+                                                                                ldrh, pw, epsc, p, g->scalars,
+                                                                                g->k_max);
         gram_partial<T, K, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RG, ldrg,
                                                                           part);
         sum_partials(part, (int)kk, mid, Mw, MG_out, s);
         gram_partial<T, K, false, false><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, nullptr, 0, 0.0, RH, ldrh,
                                                                           part);
         sum_partials(part, (int)kk, mid, Mw + kk, nullptr, s);
-        launch_apply<T, K, VEC, false, false, true>(s, n, k, 1.0, RG, ldrg, U, ldu, nullptr, 0, 0.0, Mw, -1.0, nullptr,
-                                                    0, nullptr, 0.0, RG, ldrg);
+        if (MODE == HVP)
+            launch_apply<T, K, VEC, false, false, true>(s, n, k, 1.0, RG, ldrg, U, ldu, nullptr, 0, 0.0, Mw, -1.0,
+                                                        nullptr, 0, nullptr, 0.0, RG, ldrg);
         launch_apply<T, K, VEC, false, true, true>(s, n, k, 1.0, RH, ldrh, U, ldu, nullptr, 0, 0.0, Mw + kk, -1.0, V,
                                                    ldv, Mw, -1.0, RH, ldrh);
     }
@@ -990,23 +1031,23 @@ pspec_status dispatch(Graph *g, pspec_dtype dt, int k, const void *U, int64_t ld
                                             (double *)J, ldj, p, eps, F_col, F, s, rank2);
 }
 
-template <typename T, typename WT, int K>
+template <typename T, typename WT, int K, int MODE>
 pspec_status rhvp_layout(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, double p, double eps,
                          T *RH, int64_t ldrh, T *RG, int64_t ldrg, double *MG, double *F_col, double *ws,
                          hipStream_t s) {
     if (rows_vectorisable<T, K>(k, {{U, ldu}, {V, ldv}, {RH, ldrh}, {RG, ldrg}}))
-        return launch_rhvp<T, WT, K, true>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, s);
-    return launch_rhvp<T, WT, K, false>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, s);
+        return launch_rhvp<T, WT, K, true, MODE>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, s);
+    return launch_rhvp<T, WT, K, false, MODE>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, s);
 }
 
-template <typename T, typename WT>
+template <typename T, typename WT, int MODE>
 pspec_status rhvp_k(Graph *g, int k, const void *U, int64_t ldu, const void *V, int64_t ldv, double p, double eps,
                     void *RH, int64_t ldrh, void *RG, int64_t ldrg, double *MG, double *F_col, double *ws,
                     hipStream_t s) {
-#define PSPEC_RHVP_K(KK)                                                                                          \
-    case KK:                                                                                                      \
-        return rhvp_layout<T, WT, KK>(g, k, (const T *)U, ldu, (const T *)V, ldv, p, eps, (T *)RH, ldrh, (T *)RG, \
-                                      ldrg, MG, F_col, ws, s);
+#define PSPEC_RHVP_K(KK)                                                                                         \
+    case KK:                                                                                                     \
+        return rhvp_layout<T, WT, KK, MODE>(g, k, (const T *)U, ldu, (const T *)V, ldv, p, eps, (T *)RH, ldrh,   \
+                                            (T *)RG, ldrg, MG, F_col, ws, s);
     switch (pad_k(k)) {
         PSPEC_RHVP_K(4)
         PSPEC_RHVP_K(8)
@@ -1163,34 +1204,57 @@ extern "C" pspec_status pspec_hvp_gather_floor(pspec_graph g, int k, const void 
     return st;
 }
 
-extern "C" pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
-                                   int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
-                                   double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream) {
+static pspec_status rhvp_entry(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                               int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
+                               double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream, bool fixed_u,
+                               const char *who) {
     clear_error();
-    pspec_status st = check_common(g, dt, k, U, ldu, p, "rhvp");
+    pspec_status st = check_common(g, dt, k, U, ldu, p, who);
     if (st != PSPEC_OK) return st;
-    PSPEC_ARG(eps > 0.0 && std::isfinite(eps), "rhvp: eps = %g must be positive", eps);
-    if ((st = check_out(g, dt, k, V, ldv, "V", "rhvp")) != PSPEC_OK) return st;
-    if ((st = check_out(g, dt, k, RH, ldrh, "RH", "rhvp")) != PSPEC_OK) return st;
-    if ((st = check_out(g, dt, k, RG, ldrg, "RG", "rhvp")) != PSPEC_OK) return st;
-    PSPEC_ARG(ws != nullptr, "rhvp: workspace is NULL");
-    PSPEC_ARG(((uintptr_t)ws % 256) == 0, "rhvp: workspace must be 256-byte aligned");
+    PSPEC_ARG(eps > 0.0 && std::isfinite(eps), "%s: eps = %g must be positive", who, eps);
+    if ((st = check_out(g, dt, k, V, ldv, "V", who)) != PSPEC_OK) return st;
+    if ((st = check_out(g, dt, k, RH, ldrh, "RH", who)) != PSPEC_OK) return st;
+    if ((st = check_out(g, dt, k, RG, ldrg, fixed_u ? "G" : "RG", who)) != PSPEC_OK) return st;
+    PSPEC_ARG(ws != nullptr, "%s: workspace is NULL", who);
+    PSPEC_ARG(((uintptr_t)ws % 256) == 0, "%s: workspace must be 256-byte aligned", who);
     if (ws_bytes < dense_ws_doubles(k) * sizeof(double)) {
-        set_error("rhvp: workspace of %zu bytes < %zu needed", ws_bytes, dense_ws_doubles(k) * sizeof(double));
+        set_error("%s: workspace of %zu bytes < %zu needed", who, ws_bytes, dense_ws_doubles(k) * sizeof(double));
         return PSPEC_ERR_WORKSPACE;
     }
     const size_t es = dt == PSPEC_F32 ? 4 : 8;
     const int64_t n = g->n;
+    // RG is an output (rhvp) or the given gradient (rhess, read only: may share memory with U or V)
     PSPEC_ARG(!blocks_overlap(RH, ldrh, U, ldu, n, k, es) && !blocks_overlap(RH, ldrh, V, ldv, n, k, es) &&
-                  !blocks_overlap(RG, ldrg, U, ldu, n, k, es) && !blocks_overlap(RG, ldrg, V, ldv, n, k, es) &&
+                  (fixed_u || (!blocks_overlap(RG, ldrg, U, ldu, n, k, es) && !blocks_overlap(RG, ldrg, V, ldv, n, k, es))) &&
                   !blocks_overlap(RG, ldrg, RH, ldrh, n, k, es),
-              "rhvp: RH and RG must not overlap U, V or each other");
+              "%s: RH (and RG) must not overlap the inputs or each other", who);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     double *w = static_cast<double *>(ws);
-    if (dt == PSPEC_F32) return rhvp_k<float, float>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
-    if (g->wtype == PSPEC_F32)
-        return rhvp_k<double, float>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
-    return rhvp_k<double, double>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
+#define PSPEC_RHVP_DT(MODE)                                                                                          \
+    if (dt == PSPEC_F32) return rhvp_k<float, float, MODE>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s); \
+    if (g->wtype == PSPEC_F32)                                                                                       \
+        return rhvp_k<double, float, MODE>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);     \
+    return rhvp_k<double, double, MODE>(g, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, w, s);
+    if (fixed_u) {
+        PSPEC_RHVP_DT(HESS)
+    }
+    PSPEC_RHVP_DT(HVP)
+#undef PSPEC_RHVP_DT
+}
+
+extern "C" pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                                   int64_t ldv, double p, double eps, void *RH, int64_t ldrh, void *RG, int64_t ldrg,
+                                   double *MG, double *F_col, void *ws, size_t ws_bytes, pspec_stream stream) {
+    return rhvp_entry(g, dt, k, U, ldu, V, ldv, p, eps, RH, ldrh, RG, ldrg, MG, F_col, ws, ws_bytes, stream, false,
+                      "rhvp");
+}
+
+extern "C" pspec_status pspec_rhess(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,
+                                    int64_t ldv, const void *G, int64_t ldg, double p, double eps, void *RH,
+                                    int64_t ldrh, double *MG, double *F_col, void *ws, size_t ws_bytes,
+                                    pspec_stream stream) {
+    return rhvp_entry(g, dt, k, U, ldu, V, ldv, p, eps, RH, ldrh, const_cast<void *>(G), ldg, MG, F_col, ws, ws_bytes,
+                      stream, true, "rhess");
 }
 
 extern "C" pspec_status pspec_rhvp_static(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu,

@@ -45,7 +45,11 @@ bool blocks_overlap(const void *a, int64_t lda, const void *b, int64_t ldb, int6
 namespace {
 
 constexpr int kPlanBlock = 256;  // rows per block of the schedule kernels
-constexpr int kCounters = 4;     // heavy rows, chunks, split rows, chunks of split rows
+// Per-row counters of the schedule: heavy rows, chunks of the shared list (rows of LIGHT_MAX + 1 ..
+// CHUNK edges, one chunk each), split rows (more than CHUNK edges), their chunks, and their chunks in
+// each of the kSegs column segments.
+constexpr int kCHeavy = 0, kCGlob = 1, kCSplit = 2, kCSplitChunks = 3, kCSeg = 4;
+constexpr int kCounters = kCSeg + kSegs;
 
 __global__ __launch_bounds__(kBlock) void k_check_rowptr(const int64_t *__restrict__ rowptr, int64_t n, int64_t nnz,
                                                        int *__restrict__ flag) {
@@ -69,27 +73,71 @@ __global__ __launch_bounds__(kBlock) void k_check_col(const int32_t *__restrict_
     if (bad) atomicOr(flag, 2);
 }
 
-__device__ __forceinline__ void row_counts(const int64_t *__restrict__ rowptr, int64_t n, int64_t i, int light_max,
-                                           int chunk, int64_t cnt[kCounters]) {
-    cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
-    if (i < n) {
-        const int64_t d = rowptr[i + 1] - rowptr[i];
-        if (d > light_max) {
-            const int64_t nch = (d + chunk - 1) / chunk;
-            cnt[0] = 1;
-            cnt[1] = nch;
-            cnt[2] = nch > 1 ? 1 : 0;
-            cnt[3] = nch > 1 ? nch : 0;
-        }
+// Column segment boundaries: bound[s] = the first node j with rowptr[j] >= s nnz / kSegs, so each
+// segment [bound[s], bound[s + 1]) holds an equal share of the stored entries -- and, the graph being
+// symmetric, receives an equal share of the neighbour gathers.  One thread per boundary.
+__global__ void k_seg_bounds(const int64_t *__restrict__ rowptr, int64_t n, int64_t nnz, int32_t *__restrict__ bound) {
+    const int s = threadIdx.x;
+    if (s > kSegs) return;
+    if (s == 0 || s == kSegs) {
+        bound[s] = s == 0 ? 0 : (int32_t)n;
+        return;
+    }
+    const int64_t target = (nnz * s + kSegs - 1) / kSegs;
+    int64_t lo = 0, hi = n;  // smallest j in [0, n] with rowptr[j] >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (rowptr[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    bound[s] = (int32_t)lo;
+}
+
+// First position p in [beg, end) with col[p] >= v (binary search).  For any column order the positions
+// found for increasing v never decrease, so the kSegs ranges they delimit always partition the row;
+// with ascending columns (the usual CSR) each range holds exactly the row's neighbours in one segment.
+__device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ col, int64_t beg, int64_t end, int32_t v) {
+    int64_t lo = beg, hi = end;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (col[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The row's counters and, for split rows, its segment ranges pos[0..kSegs].
+__device__ __forceinline__ void row_counts(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                           const int32_t *__restrict__ bound, int64_t n, int64_t i, int light_max,
+                                           int chunk, int64_t cnt[kCounters], int64_t pos[kSegs + 1]) {
+    for (int q = 0; q < kCounters; ++q) cnt[q] = 0;
+    if (i >= n) return;
+    const int64_t beg = rowptr[i], end = rowptr[i + 1], d = end - beg;
+    if (d <= light_max) return;
+    cnt[kCHeavy] = 1;
+    if (d <= chunk) {
+        cnt[kCGlob] = 1;
+        return;
+    }
+    cnt[kCSplit] = 1;
+    pos[0] = beg;
+    pos[kSegs] = end;
+    for (int s = 1; s < kSegs; ++s) pos[s] = lower_pos(col, pos[s - 1], end, bound[s]);
+    for (int s = 0; s < kSegs; ++s) {
+        const int64_t c = (pos[s + 1] - pos[s] + chunk - 1) / chunk;
+        cnt[kCSeg + s] = c;
+        cnt[kCSplitChunks] += c;
     }
 }
 
-__global__ __launch_bounds__(kPlanBlock) void k_plan_count(const int64_t *__restrict__ rowptr, int64_t n, int light_max,
+__global__ __launch_bounds__(kPlanBlock) void k_plan_count(const int64_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ bound, int64_t n, int light_max,
                                                          int chunk, int64_t *__restrict__ bcount) {
     __shared__ int64_t s[kCounters][kPlanBlock];
     const int t = threadIdx.x;
-    int64_t cnt[kCounters];
-    row_counts(rowptr, n, (int64_t)blockIdx.x * kPlanBlock + t, light_max, chunk, cnt);
+    int64_t cnt[kCounters], pos[kSegs + 1];
+    row_counts(rowptr, col, bound, n, (int64_t)blockIdx.x * kPlanBlock + t, light_max, chunk, cnt, pos);
     for (int q = 0; q < kCounters; ++q) s[q][t] = cnt[q];
     __syncthreads();
     for (int o = kPlanBlock / 2; o > 0; o >>= 1) {
@@ -108,13 +156,15 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(int64_t *__restrict__ 
     const int t = threadIdx.x;
     const int64_t seg = (nb + kPlanBlock - 1) / kPlanBlock;
     const int64_t b0 = t * seg, b1 = (b0 + seg < nb) ? b0 + seg : nb;
-    int64_t loc[kCounters] = {0, 0, 0, 0};
+    int64_t loc[kCounters];
+    for (int q = 0; q < kCounters; ++q) loc[q] = 0;
     for (int64_t b = b0; b < b1; ++b)
         for (int q = 0; q < kCounters; ++q) loc[q] += bcount[b * kCounters + q];
     for (int q = 0; q < kCounters; ++q) s[q][t] = loc[q];
     __syncthreads();
     if (t == 0) {
-        int64_t run[kCounters] = {0, 0, 0, 0};
+        int64_t run[kCounters];
+        for (int q = 0; q < kCounters; ++q) run[q] = 0;
         for (int i = 0; i < kPlanBlock; ++i)
             for (int q = 0; q < kCounters; ++q) {
                 const int64_t v = s[q][i];
@@ -134,14 +184,24 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scan(int64_t *__restrict__ 
         }
 }
 
-__global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restrict__ rowptr, int64_t n, int light_max,
-                                                        int chunk, const int64_t *__restrict__ boff,
+// Chunk list layout: the chunks of column segment 0, ..., segment kSegs - 1 (base.seg[s]), then the
+// shared list (base.glob).  Each split row's chunks take consecutive scratch slots in (segment,
+// position) order, the order in which they are combined.
+struct ChunkBases {
+    int64_t seg[kSegs + 1];
+    int64_t glob;
+};
+
+__global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ bound, int64_t n, int light_max,
+                                                        int chunk, const int64_t *__restrict__ boff, ChunkBases base,
                                                         Chunk *__restrict__ chunks, Split *__restrict__ splits) {
     __shared__ int64_t s[kCounters][kPlanBlock];
     const int t = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kPlanBlock + t;
-    int64_t cnt[kCounters];
-    row_counts(rowptr, n, i, light_max, chunk, cnt);
+    int64_t cnt[kCounters], pos[kSegs + 1];
+    row_counts(rowptr, col, bound, n, i, light_max, chunk, cnt, pos);
     for (int q = 0; q < kCounters; ++q) s[q][t] = cnt[q];
     __syncthreads();
     // Hillis-Steele inclusive scan over the block
@@ -152,73 +212,151 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restr
         for (int q = 0; q < kCounters; ++q) s[q][t] += v[q];
         __syncthreads();
     }
-    if (cnt[1] == 0) return;
-    const int64_t cbase = boff[(int64_t)blockIdx.x * kCounters + 1] + s[1][t] - cnt[1];
-    const int64_t sbase = boff[(int64_t)blockIdx.x * kCounters + 2] + s[2][t] - cnt[2];
-    const int64_t xbase = boff[(int64_t)blockIdx.x * kCounters + 3] + s[3][t] - cnt[3];  // first scratch slot
-    const int64_t beg = rowptr[i], end = rowptr[i + 1];
-    const bool split = cnt[1] > 1;
-    for (int64_t q = 0; q < cnt[1]; ++q) {
+    if (cnt[kCHeavy] == 0) return;
+    auto first = [&](int q) { return boff[(int64_t)blockIdx.x * kCounters + q] + s[q][t] - cnt[q]; };
+    if (cnt[kCGlob]) {
         Chunk c;
-        c.beg = beg + q * chunk;
-        c.end = (c.beg + chunk < end) ? c.beg + chunk : end;
+        c.beg = rowptr[i];
+        c.end = rowptr[i + 1];
         c.row = (int32_t)i;
-        c.slot = split ? (int32_t)(xbase + q) : -1;
-        chunks[cbase + q] = c;
+        c.slot = -1;
+        chunks[base.glob + first(kCGlob)] = c;
+        return;
     }
-    if (split) {
-        Split sp;
-        sp.row = (int32_t)i;
-        sp.first = (int32_t)xbase;
-        sp.count = (int32_t)cnt[1];
-        sp.pad = 0;
-        splits[sbase] = sp;
+    const int64_t xbase = first(kCSplitChunks);  // first scratch slot of the row
+    int64_t slot = xbase;
+    for (int sg = 0; sg < kSegs; ++sg) {
+        const int64_t c0 = base.seg[sg] + first(kCSeg + sg);
+        for (int64_t q = 0; q < cnt[kCSeg + sg]; ++q) {
+            Chunk c;
+            c.beg = pos[sg] + q * chunk;
+            c.end = (c.beg + chunk < pos[sg + 1]) ? c.beg + chunk : pos[sg + 1];
+            c.row = (int32_t)i;
+            c.slot = (int32_t)slot++;
+            chunks[c0 + q] = c;
+        }
     }
+    Split sp;
+    sp.row = (int32_t)i;
+    sp.first = (int32_t)xbase;
+    sp.count = (int32_t)cnt[kCSplitChunks];
+    sp.pad = 0;
+    splits[first(kCSplit)] = sp;
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Layout of the caller's workspace: every part bounded from (n, nnz, k_max) alone.
+// Layout of the caller's workspace.  The first part depends on (n, k_max) only: the schedule kernels'
+// counters, the column-segment boundaries and the FP64 partial sums of the edge pass.  The schedule
+// itself (chunk list, split-row list, split-row scratch) follows, sized by the counts of the graph:
+// exact once they are known, otherwise by bounds from (n, nnz) alone --
 //   heavy rows   <= min(n, nnz / (LIGHT_MAX + 1))      (each holds more than LIGHT_MAX edges)
-//   chunks       <= nnz / CHUNK + heavy rows           (ceil(d / C) <= floor(d / C) + 1, sum floor <= nnz / C)
 //   split rows   <= min(n, nnz / (CHUNK + 1))
-//   split chunks <= nnz / CHUNK + split rows
+//   split chunks <= nnz / CHUNK + kSegs split rows     (sum over segments of ceil(d_s / C) <= d / C + kSegs)
+//   chunks       <= heavy rows + split chunks
 //   partial rows  = light tiles + kHeavyGridCap
 struct WsLayout {
-    size_t chunks = 0, splits = 0, part = 0, red1 = 0, sc = 0, scr = 0, bcount = 0, tot = 0, total = 0;
-    int64_t max_chunks = 0, max_split = 0, max_split_chunks = 0;
+    size_t bcount = 0, tot = 0, bound = 0, part = 0, red1 = 0, sc = 0, chunks = 0, splits = 0, scr = 0;
+    size_t fixed = 0, total = 0;
 };
 
-WsLayout ws_layout(int64_t n, int64_t nnz, int k_max) {
+WsLayout ws_layout(int64_t n, int k_max, int64_t n_chunks, int64_t n_split, int64_t n_split_chunks) {
     WsLayout L;
-    const int64_t max_heavy = std::min<int64_t>(n, nnz / (PSPEC_LIGHT_MAX + 1));
-    L.max_chunks = nnz / PSPEC_CHUNK + max_heavy;
-    L.max_split = std::min<int64_t>(n, nnz / (PSPEC_CHUNK + 1));
-    L.max_split_chunks = nnz / PSPEC_CHUNK + L.max_split;
     const int64_t tiles = (n + kTileRows - 1) / kTileRows;
     const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
     const size_t parts[] = {
-        align256(sizeof(Chunk) * (size_t)L.max_chunks),
-        align256(sizeof(Split) * (size_t)L.max_split),
+        align256(sizeof(int64_t) * (size_t)nb * kCounters),
+        align256(sizeof(int64_t) * kCounters + sizeof(int)),
+        align256(sizeof(int32_t) * (kSegs + 1)),
         align256(sizeof(double) * (size_t)(tiles + kHeavyGridCap) * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kReduceSlices * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kScalars * (size_t)k_max),
-        align256(sizeof(double) * (size_t)L.max_split_chunks * 2 * (size_t)k_max),
-        align256(sizeof(int64_t) * (size_t)nb * kCounters),
-        align256(sizeof(int64_t) * kCounters + sizeof(int)),
+        align256(sizeof(Chunk) * (size_t)n_chunks),
+        align256(sizeof(Split) * (size_t)n_split),
+        align256(sizeof(double) * (size_t)n_split_chunks * 2 * (size_t)k_max),
     };
-    size_t *dst[] = {&L.chunks, &L.splits, &L.part, &L.red1, &L.sc, &L.scr, &L.bcount, &L.tot};
+    size_t *dst[] = {&L.bcount, &L.tot, &L.bound, &L.part, &L.red1, &L.sc, &L.chunks, &L.splits, &L.scr};
     size_t off = 0;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 9; ++i) {
         *dst[i] = off;
         off += parts[i];
+        if (i == 5) L.fixed = off;
     }
     L.total = off;
     return L;
 }
 
+WsLayout ws_bound(int64_t n, int64_t nnz, int k_max) {
+    const int64_t max_heavy = std::min<int64_t>(n, nnz / (PSPEC_LIGHT_MAX + 1));
+    const int64_t max_split = std::min<int64_t>(n, nnz / (PSPEC_CHUNK + 1));
+    const int64_t max_split_chunks = nnz / PSPEC_CHUNK + (int64_t)kSegs * max_split;
+    return ws_layout(n, k_max, max_heavy + max_split_chunks, max_split, max_split_chunks);
+}
+
 bool ws_args_ok(int64_t n, int64_t nnz, int k_max) {
     return n >= 1 && nnz >= 0 && k_max >= 1 && k_max <= PSPEC_K_MAX && n < ((int64_t)1 << 31) - 1;
+}
+
+// The counts of a graph's schedule (validated CSR): tot[kCounters] from the counting kernels.
+struct Plan {
+    int64_t tot[kCounters];
+    int64_t n_chunks() const { return tot[kCGlob] + tot[kCSplitChunks]; }
+};
+
+// Shared front half of create and the workspace query: argument checks, CSR validation, segment
+// boundaries and schedule counts in the workspace's fixed part; synchronises the stream once.
+pspec_status plan_counts(const char *who, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col, int k_max,
+                         void *workspace, size_t ws_bytes, hipStream_t s, WsLayout &L, Plan &plan) {
+    PSPEC_ARG(n >= 1, "%s: n = %lld < 1", who, (long long)n);
+    PSPEC_ARG(nnz >= 0, "%s: nnz = %lld < 0", who, (long long)nnz);
+    PSPEC_ARG(rowptr != nullptr, "%s: rowptr is NULL", who);
+    PSPEC_ARG(nnz == 0 || col != nullptr, "%s: col is NULL", who);
+    PSPEC_UNSUP(k_max >= 1 && k_max <= PSPEC_K_MAX, "%s: k_max = %d outside 1..%d", who, k_max, PSPEC_K_MAX);
+    PSPEC_UNSUP(n < ((int64_t)1 << 31) - 1, "%s: n = %lld needs 64-bit node ids", who, (long long)n);
+    PSPEC_ARG(workspace != nullptr, "%s: workspace is NULL", who);
+    PSPEC_ARG(((uintptr_t)workspace % 256) == 0, "%s: workspace must be 256-byte aligned", who);
+    L = ws_layout(n, k_max, 0, 0, 0);
+    if (ws_bytes < L.fixed) {
+        set_error("%s: workspace of %zu bytes < %zu needed before the schedule", who, ws_bytes, L.fixed);
+        return PSPEC_ERR_WORKSPACE;
+    }
+    char *mem = static_cast<char *>(workspace);
+    int64_t *bcount = reinterpret_cast<int64_t *>(mem + L.bcount);
+    int64_t *tot = reinterpret_cast<int64_t *>(mem + L.tot);
+    int *flag = reinterpret_cast<int *>(tot + kCounters);
+    int32_t *bound = reinterpret_cast<int32_t *>(mem + L.bound);
+    const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
+    PSPEC_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_check_rowptr<<<(unsigned)((n + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(rowptr, n, nnz, flag);
+    if (nnz > 0) {
+        const int64_t want = (nnz + kBlock - 1) / kBlock;
+        k_check_col<<<(unsigned)(want < 65536 ? want : 65536), kBlock, 0, s>>>(col, nnz, n, flag);
+    }
+    PSPEC_HIP(hipGetLastError());
+    int host_flag = 0;
+    PSPEC_HIP(hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PSPEC_HIP(hipStreamSynchronize(s));
+    if (host_flag != 0) {
+        set_error("%s: malformed CSR (%s%s)", who, (host_flag & 1) ? "row pointers" : "",
+                  (host_flag & 2) ? " column indices out of range" : "");
+        return PSPEC_ERR_ARG;
+    }
+    // only a validated CSR is searched: the boundaries and the counts read rowptr and col
+    k_seg_bounds<<<1, 64, 0, s>>>(rowptr, n, nnz, bound);
+    k_plan_count<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, bound, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount);
+    k_plan_scan<<<1, kPlanBlock, 0, s>>>(bcount, nb, tot);
+    PSPEC_HIP(hipGetLastError());
+    PSPEC_HIP(hipMemcpyAsync(plan.tot, tot, sizeof(int64_t) * kCounters, hipMemcpyDeviceToHost, s));
+    PSPEC_HIP(hipStreamSynchronize(s));
+    // the bounds of ws_bound hold for every valid CSR; a violation means the counts are wrong
+    const WsLayout B = ws_bound(n, nnz, k_max);
+    if (ws_layout(n, k_max, plan.n_chunks(), plan.tot[kCSplit], plan.tot[kCSplitChunks]).total > B.total) {
+        set_error("%s: schedule (%lld chunks, %lld split rows, %lld split chunks) exceeds its bound", who,
+                  (long long)plan.n_chunks(), (long long)plan.tot[kCSplit], (long long)plan.tot[kCSplitChunks]);
+        return PSPEC_ERR_HIP;
+    }
+    L = ws_layout(n, k_max, plan.n_chunks(), plan.tot[kCSplit], plan.tot[kCSplitChunks]);
+    return PSPEC_OK;
 }
 
 }  // namespace
@@ -229,7 +367,26 @@ using namespace pspec;
 extern "C" const char *pspec_last_error(void) { return g_err; }
 
 extern "C" size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max) {
-    return ws_args_ok(n, nnz, k_max) ? ws_layout(n, nnz, k_max).total : 0;
+    return ws_args_ok(n, nnz, k_max) ? ws_bound(n, nnz, k_max).total : 0;
+}
+
+extern "C" size_t pspec_graph_count_workspace_bytes(int64_t n, int k_max) {
+    return ws_args_ok(n, 0, k_max) ? ws_layout(n, k_max, 0, 0, 0).fixed : 0;
+}
+
+extern "C" pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                                                    int k_max, void *workspace, size_t ws_bytes, pspec_stream stream,
+                                                    size_t *needed) {
+    clear_error();
+    PSPEC_ARG(needed != nullptr, "graph_exact_workspace: needed is NULL");
+    *needed = 0;
+    WsLayout L;
+    Plan plan;
+    const pspec_status st = plan_counts("graph_exact_workspace", n, nnz, rowptr, col, k_max, workspace, ws_bytes,
+                                        reinterpret_cast<hipStream_t>(stream), L, plan);
+    if (st != PSPEC_OK) return st;
+    *needed = L.total;
+    return PSPEC_OK;
 }
 
 extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
@@ -238,55 +395,25 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     clear_error();
     PSPEC_ARG(out != nullptr, "graph_create: out is NULL");
     *out = nullptr;
-    PSPEC_ARG(n >= 1, "graph_create: n = %lld < 1", (long long)n);
-    PSPEC_ARG(nnz >= 0, "graph_create: nnz = %lld < 0", (long long)nnz);
-    PSPEC_ARG(rowptr != nullptr, "graph_create: rowptr is NULL");
-    PSPEC_ARG(nnz == 0 || (col != nullptr && w != nullptr), "graph_create: col or w is NULL");
+    PSPEC_ARG(nnz == 0 || w != nullptr, "graph_create: w is NULL");
     PSPEC_ARG(wtype == PSPEC_F32 || wtype == PSPEC_F64, "graph_create: bad wtype %d", (int)wtype);
-    PSPEC_UNSUP(k_max >= 1 && k_max <= PSPEC_K_MAX, "graph_create: k_max = %d outside 1..%d", k_max, PSPEC_K_MAX);
-    PSPEC_UNSUP(n < ((int64_t)1 << 31) - 1, "graph_create: n = %lld needs 64-bit node ids", (long long)n);
-    PSPEC_ARG(workspace != nullptr, "graph_create: workspace is NULL");
-    PSPEC_ARG(((uintptr_t)workspace % 256) == 0, "graph_create: workspace must be 256-byte aligned");
-    const WsLayout L = ws_layout(n, nnz, k_max);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    WsLayout L;
+    Plan plan;
+    pspec_status st = plan_counts("graph_create", n, nnz, rowptr, col, k_max, workspace, ws_bytes, s, L, plan);
+    if (st != PSPEC_OK) return st;
     if (ws_bytes < L.total) {
-        set_error("graph_create: workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+        set_error("graph_create: workspace of %zu bytes < %zu this graph's schedule needs", ws_bytes, L.total);
         return PSPEC_ERR_WORKSPACE;
     }
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     char *mem = static_cast<char *>(workspace);
-    int64_t *bcount = reinterpret_cast<int64_t *>(mem + L.bcount);
-    int64_t *tot = reinterpret_cast<int64_t *>(mem + L.tot);
-    int *flag = reinterpret_cast<int *>(tot + kCounters);
+    ChunkBases base;
+    base.seg[0] = 0;
+    for (int sg = 0; sg < kSegs; ++sg) base.seg[sg + 1] = base.seg[sg] + plan.tot[kCSeg + sg];
+    base.glob = base.seg[kSegs];
 
     int dev = 0;
     PSPEC_HIP(hipGetDevice(&dev));
-    const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
-    PSPEC_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-    k_check_rowptr<<<(unsigned)((n + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(rowptr, n, nnz, flag);
-    if (nnz > 0) {
-        const int64_t want = (nnz + kBlock - 1) / kBlock;
-        k_check_col<<<(unsigned)(want < 65536 ? want : 65536), kBlock, 0, s>>>(col, nnz, n, flag);
-    }
-    k_plan_count<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount);
-    k_plan_scan<<<1, kPlanBlock, 0, s>>>(bcount, nb, tot);
-    PSPEC_HIP(hipGetLastError());
-    int64_t host_tot[kCounters + 1];
-    PSPEC_HIP(hipMemcpyAsync(host_tot, tot, sizeof(int64_t) * kCounters + sizeof(int), hipMemcpyDeviceToHost, s));
-    PSPEC_HIP(hipStreamSynchronize(s));
-    int host_flag = 0;
-    std::memcpy(&host_flag, &host_tot[kCounters], sizeof(int));
-    if (host_flag != 0) {
-        set_error("graph_create: malformed CSR (%s%s)", (host_flag & 1) ? "row pointers" : "",
-                  (host_flag & 2) ? " column indices out of range" : "");
-        return PSPEC_ERR_ARG;
-    }
-    // the bounds of ws_layout hold for every valid CSR; a violation means the counts are wrong
-    if (host_tot[1] > L.max_chunks || host_tot[2] > L.max_split || host_tot[3] > L.max_split_chunks) {
-        set_error("graph_create: schedule (%lld chunks, %lld split rows, %lld split chunks) exceeds its bound",
-                  (long long)host_tot[1], (long long)host_tot[2], (long long)host_tot[3]);
-        return PSPEC_ERR_HIP;
-    }
-
     pspec_graph g = new pspec_graph_s();
     g->n = n;
     g->nnz = nnz;
@@ -297,24 +424,31 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->k_max = k_max;
     g->device = dev;
     g->tiles = (n + kTileRows - 1) / kTileRows;
-    g->heavy_rows = host_tot[0];
-    g->n_chunks = host_tot[1];
-    g->n_split = host_tot[2];
-    g->n_split_chunks = host_tot[3];
+    g->heavy_rows = plan.tot[kCHeavy];
+    g->n_chunks = plan.n_chunks();
+    g->n_split = plan.tot[kCSplit];
+    g->n_split_chunks = plan.tot[kCSplitChunks];
+    for (int sg = 0; sg <= kSegs; ++sg) g->seg_chunk_base[sg] = base.seg[sg];
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
     g->cus = cus > 0 ? cus : 1;
-    const int64_t hwant = (g->n_chunks + 3) / 4;
-    g->heavy_grid_max = std::min<int64_t>(std::min<int64_t>(hwant, (int64_t)kHeavyPerCUMax * g->cus), kHeavyGridCap);
+    // a multiple of kSegs (every segment served by as many workgroups), at least kSegs
+    const int64_t hwant = std::max<int64_t>((g->n_chunks + 3) / 4, kSegs);
+    const int64_t hmax = std::min<int64_t>(std::min<int64_t>(hwant, (int64_t)kHeavyPerCUMax * g->cus), kHeavyGridCap);
+    g->heavy_grid_max = std::max<int64_t>(hmax / kSegs * kSegs, kSegs);
     g->chunks = reinterpret_cast<Chunk *>(mem + L.chunks);
     g->splits = reinterpret_cast<Split *>(mem + L.splits);
     g->partials = reinterpret_cast<double *>(mem + L.part);
     g->red1 = reinterpret_cast<double *>(mem + L.red1);
     g->scalars = reinterpret_cast<double *>(mem + L.sc);
     g->chunk_scratch = reinterpret_cast<double *>(mem + L.scr);
-    if (g->n_chunks > 0)
-        k_plan_emit<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount, g->chunks,
-                                                         g->splits);
+    if (g->n_chunks > 0) {
+        const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
+        k_plan_emit<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, reinterpret_cast<const int32_t *>(mem + L.bound),
+                                                         n, PSPEC_LIGHT_MAX, PSPEC_CHUNK,
+                                                         reinterpret_cast<const int64_t *>(mem + L.bcount), base,
+                                                         g->chunks, g->splits);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         delete g;

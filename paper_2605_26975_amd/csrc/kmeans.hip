@@ -5,9 +5,9 @@
 // centroid as sum_t (x_t - c_t)^2 in t order with no fused multiply-add, and keeps the first
 // centroid of smallest distance, so labels and distances are a plain function of the inputs (no
 // summation order to choose).  The per-cluster statistics (coordinate sums, count, distance sum)
-// are gathered per wave in one of three ways (see Stat below): in each lane's registers (few
-// clusters and columns), as one-hot products on the FP64 matrix cores (up to 16 columns), or by a
-// DPP wave reduction per (cluster, column) pair and 64-row batch.  Every way adds in a fixed order;
+// are gathered per wave in one of two ways (see Stat below): in each lane's registers (at most 4
+// clusters of at most 8 columns), or as one-hot products on the FP64 matrix cores (the rows staged
+// as [x | 1 | dist] in LDS, in two halves above 16 columns).  Both add in a fixed order;
 // the four waves of a workgroup are added in order into one partial per workgroup, and the
 // kDenseBlocks partials by the fixed two-level tree of the dense kernels, so the statistics are
 // bit-reproducible from run to run.  The work is one read of the block plus the optional label and

@@ -77,12 +77,16 @@ class Solver:
     def dot(self, A, B) -> float:
         return float(pspec.dot(A, B).item())
 
-    def hess(self, U, p, X, out):
-        """Riemannian Hessian at U applied to the tangent vector X: one fused library call (edge
-        pass, epilogue, both Gram matrices and the projection); the Riemannian gradient it also
-        returns goes to a scratch block."""
+    def hess(self, U, p, X, out, G=None):
+        """Riemannian Hessian at U applied to the tangent vector X.  With G, the Euclidean gradient at
+        U (computed once per Newton step, as the truncated-CG loops below do), one pspec_rhess call
+        (edge pass without the gradient rows, epilogue, Gram matrices, projection); without it, G is
+        formed first."""
         if self.hessian == "exact":
-            pspec.rhvp(self.graph, U, X, p, self.eps, RH=out, RG=self.HV, MG=self.MG)
+            if G is None:
+                pspec.grad(self.graph, U, p, G=self.G)
+                G = self.G
+            pspec.rhess(self.graph, U, X, G, p, self.eps, RH=out, MG=self.MG)
             return out
         # sparse-only operator: Euclidean product, then P_U(H X) - X (U^T G)
         pspec.hvp(self.graph, U, X, p, self.eps, HV=self.HV, G=self.G, sparse_only=True)
@@ -116,7 +120,7 @@ class Solver:
             nt = 0
             for j in range(opt.tcg_max):
                 nt = j + 1
-                self.hess(U, p, self.delta, self.Hd)
+                self.hess(U, p, self.delta, self.Hd, G=self.G)
                 dHd = self.dot(self.delta, self.Hd)
                 if dHd <= 0.0:
                     if j == 0:
@@ -201,7 +205,7 @@ def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | Non
         nt = 0
         for j in range(opt.tcg_max):
             nt = j + 1
-            s.hess(U, p, s.delta, s.Hd)
+            s.hess(U, p, s.delta, s.Hd, G=s.G)
             dHd = s.dot(s.delta, s.Hd)
             alpha = rr / dHd if dHd > 0.0 else 0.0
             e_e_new = e_e + 2.0 * alpha * e_d + alpha * alpha * d_d
@@ -437,55 +441,6 @@ def delaunay_study(r: int, k: int = 4, p: float = 1.2, step: float = 0.2, dtype=
     return out
 
 
-def sbm_study(k: int = 16, p: float = 1.1, step: float = 0.2, dtype=torch.float32, seed: int = 0,
-              opt: TrustRegionOptions | None = None, log=print) -> dict:
-    """The whole pipeline on the 8M-node stochastic block model of the benchmark (16 planted blocks
-    of 500,000 nodes, mean degree 12): its isolated vertices are set aside first (each is a
-    connected component, so its indicator column has F_p = 0 for every p and would be a trivial
-    minimiser once p < 2), the rest is clustered by the trust-region continuation and k-means, and
-    after every level the labels are scored against the planted blocks (matched accuracy over the
-    clustered vertices) and by RCut, next to the RCut of the planted partition itself (the method
-    minimises RCut, which need not favour the planted blocks).  Isolated vertices get the label -1."""
-    import time
-
-    from . import gen
-
-    t0 = time.perf_counter()
-    g0 = gen.CONFIGS["sbm8m"]["graph"]()
-    bs = g0.meta["labels_block"]
-    g, ids = gen.induced(g0, np.diff(g0.rowptr) > 0, "connected")
-    truth = ids // bs
-    t_graph = time.perf_counter() - t0
-    dg = pspec.Graph.from_host(g, "cuda", k_max=k)
-    solver = Solver(dg, k, dtype, 1e-8)
-    U = orthonormal_start(g.n, k, seed, dtype, "cuda")
-    out = {"n": g0.n, "isolated": int(g0.n - g.n), "k": k, "dtype": str(dtype).replace("torch.", ""),
-           "graph_seconds": round(t_graph, 2), "rcut_planted": rcut(g.rowptr, g.col, g.w, truth), "levels": []}
-    log(f"sbm8m: {g.n} of {g0.n} vertices have neighbours; graph {t_graph:.1f}s; "
-        f"RCut of the planted blocks {out['rcut_planted']:.5f}")
-    for pl in p_levels(p, step):
-        t1 = time.perf_counter()
-
-        def every10(it, F, gn, nt, pl=pl):
-            if it % 10 == 0:
-                log(f"sbm8m p={pl:.2f}   outer {it:3d} F {F:.6e} |g| {gn:.2e} tcg {nt}")
-
-        U, info = rtr(solver, U, pl, opt, every10)
-        torch.cuda.synchronize()
-        t_solve = time.perf_counter() - t1
-        labels, _, _ = kmeans_gpu(U, k, seed=seed)
-        lev = {"p": pl, "outer": info.iterations, "tcg": int(sum(info.tcg_iterations)), "F": info.F[-1],
-               "grad_rel": info.grad_norm[-1] / info.grad_norm[0], "rcut": rcut(g.rowptr, g.col, g.w, labels),
-               "accuracy": matched_accuracy(labels, truth), "solve_seconds": round(t_solve, 2)}
-        out["levels"].append(lev)
-        log(f"sbm8m p={pl:.2f} outer {lev['outer']:3d} tcg {lev['tcg']:5d} F {lev['F']:.6e} "
-            f"|g|/|g0| {lev['grad_rel']:.1e} RCut {lev['rcut']:.5f} accuracy {lev['accuracy']:.5f} {t_solve:.1f}s")
-    full = np.full(g0.n, -1, dtype=np.int64)
-    full[ids] = labels
-    out["labels"] = full
-    return out
-
-
 def _time_rhvp(dg: pspec.Graph, U: torch.Tensor, p: float, reps: int = 20) -> float:
     """Milliseconds per Riemannian HVP call (pspec_rhvp) at U along V = U."""
     RH, RG = torch.empty_like(U), torch.empty_like(U)
@@ -506,8 +461,6 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description="p-spectral clustering of Delaunay graphs of 2^r random points "
                                              "in the unit square: RCut at p = 2 against the smallest p")
-    ap.add_argument("--graph", choices=["delaunay", "sbm8m"], default="delaunay",
-                    help="Delaunay graphs of 2^r points (--r), or the 8M-node SBM with planted blocks")
     ap.add_argument("--r", type=int, nargs="+", default=[16])
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--p", type=float, default=1.2)
@@ -528,11 +481,6 @@ def main(argv=None):
     rel = a.rel_tol if a.rel_tol is not None else (1e-6 if dtype == torch.float64 else 1e-4)
     opt = TrustRegionOptions(max_outer=a.max_outer, tcg_max=a.tcg_max, rel_tol=rel)
     spec = TrustRegionOptions(max_outer=a.spec_max_outer, tcg_max=a.spec_tcg_max, rel_tol=rel)
-    if a.graph == "sbm8m":
-        res = sbm_study(a.k, a.p, a.step, dtype, a.seed, opt, log=lambda s: print(s, flush=True))
-        res.pop("labels")
-        print(json.dumps(res), flush=True)
-        return
     for r in a.r:
         res = delaunay_study(r, a.k, a.p, a.step, dtype, a.seed, opt, a.save,
                              log=lambda s: print(s, flush=True), spec_opt=spec, order=a.order, resume=a.resume)

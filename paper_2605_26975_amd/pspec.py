@@ -60,6 +60,7 @@ def lib() -> ctypes.CDLL:
         "pspec_hvp_gather_floor": [vp, i32, vp, i64, vp, i64, vp, i64, vp, i64, vp],
         "pspec_rhvp": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp, sz, vp],
         "pspec_rhvp_static": [vp, i32, i32, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, i64, vp, vp, vp],
+        "pspec_rhess": [vp, i32, i32, vp, i64, vp, i64, vp, i64, dbl, dbl, vp, i64, vp, vp, vp, sz, vp],
         "pspec_project": [i64, i32, i32, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, sz, vp],
         "pspec_retract": [i64, i32, i32, vp, i64, vp, i64, dbl, vp, i64, vp, vp, sz, vp],
         "pspec_dot": [i64, i32, i32, vp, i64, vp, i64, vp, vp, sz, vp],
@@ -73,6 +74,10 @@ def lib() -> ctypes.CDLL:
         f.restype = ctypes.c_int
     L.pspec_graph_workspace_bytes.argtypes = [i64, i64, i32]
     L.pspec_graph_workspace_bytes.restype = sz
+    L.pspec_graph_count_workspace_bytes.argtypes = [i64, i32]
+    L.pspec_graph_count_workspace_bytes.restype = sz
+    L.pspec_graph_exact_workspace.argtypes = [i64, i64, vp, vp, i32, vp, sz, vp, ctypes.POINTER(sz)]
+    L.pspec_graph_exact_workspace.restype = ctypes.c_int
     L.pspec_dense_workspace_bytes.argtypes = [i32]
     L.pspec_dense_workspace_bytes.restype = sz
     L.pspec_kmeans_workspace_bytes.argtypes = [i32, i32]
@@ -86,10 +91,11 @@ def lib() -> ctypes.CDLL:
 def exported_symbols() -> list[str]:
     """Names of the entry points the binding declares (all must resolve in the library)."""
     return [
-        "pspec_graph_workspace_bytes", "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info",
+        "pspec_graph_workspace_bytes", "pspec_graph_count_workspace_bytes", "pspec_graph_exact_workspace",
+        "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info",
         "pspec_graph_set_timing_events",
         "pspec_objective", "pspec_grad",
-        "pspec_hvp", "pspec_hvp_sparse", "pspec_hvp_gather_floor", "pspec_rhvp", "pspec_rhvp_static", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
+        "pspec_hvp", "pspec_hvp_sparse", "pspec_hvp_gather_floor", "pspec_rhvp", "pspec_rhvp_static", "pspec_rhess", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
         "pspec_axpby", "pspec_kmeans_workspace_bytes", "pspec_kmeans_step", "pspec_rcm_order",
         "pspec_last_error",
     ]
@@ -187,13 +193,19 @@ class Graph:
         self.k_max = k_max
         self.device = rowptr.device
         self._h = ctypes.c_void_p()
-        nbytes = int(lib().pspec_graph_workspace_bytes(self.n, self.nnz, k_max))
-        if nbytes == 0:
+        if int(lib().pspec_graph_workspace_bytes(self.n, self.nnz, k_max)) == 0:
             raise PSpecArgError(f"graph_create: n = {self.n}, nnz = {self.nnz}, k_max = {k_max} rejected")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         with torch.cuda.device(self.device):
+            # exact sizing: count the schedule in the fixed part, then grow the buffer to what it needs
+            nfix = int(lib().pspec_graph_count_workspace_bytes(self.n, k_max))
+            tmp = torch.empty(nfix, dtype=torch.uint8, device=self.device)
+            need = ctypes.c_size_t()
+            _check(lib().pspec_graph_exact_workspace(self.n, self.nnz, rowptr.data_ptr(), col.data_ptr(), k_max,
+                                                     tmp.data_ptr(), nfix, _stream(self.device), ctypes.byref(need)))
+            del tmp
+            self.workspace = torch.empty(need.value, dtype=torch.uint8, device=self.device)
             _check(lib().pspec_graph_create(self.n, self.nnz, rowptr.data_ptr(), col.data_ptr(), w.data_ptr(),
-                                            _dtype_code(w), k_max, self.workspace.data_ptr(), nbytes,
+                                            _dtype_code(w), k_max, self.workspace.data_ptr(), need.value,
                                             _stream(self.device), ctypes.byref(self._h)))
 
     @classmethod
@@ -335,6 +347,26 @@ def rhvp(graph: Graph, U: torch.Tensor, V: torch.Tensor, p: float, eps: float = 
                             float(eps), RH.data_ptr(), RH.stride(0), RG.data_ptr(), RG.stride(0),
                             MG.data_ptr(), F_col.data_ptr(), ws.data_ptr(), ws.numel(), _stream(U.device)))
     return RH, RG, MG, F_col
+
+
+def rhess(graph: Graph, U: torch.Tensor, V: torch.Tensor, G: torch.Tensor, p: float, eps: float = 1e-8,
+          RH: torch.Tensor | None = None, MG: torch.Tensor | None = None, F_col: torch.Tensor | None = None):
+    """Riemannian Hessian at U applied to the tangent vector V, with U's Euclidean gradient G given
+    (pspec_rhess, the form for the truncated-CG loop of one Newton step): returns (RH, MG, F_col)."""
+    ldu = _on_graph(graph, U)
+    ldv = _block(V, "V", like=U)
+    ldg = _block(G, "G", like=U)
+    k = U.shape[1]
+    RH = _out_block(RH, "RH", U)
+    if MG is None:
+        MG = torch.empty((k, k), dtype=torch.float64, device=U.device)
+    _fp64_vec(MG, "MG", k * k, U.device)
+    F_col = _fcol(F_col, k, U.device)
+    ws = _dense_ws(U.device, k)
+    _check(lib().pspec_rhess(graph.handle, _dtype_code(U), k, U.data_ptr(), ldu, V.data_ptr(), ldv, G.data_ptr(), ldg,
+                             float(p), float(eps), RH.data_ptr(), RH.stride(0), MG.data_ptr(), F_col.data_ptr(),
+                             ws.data_ptr(), ws.numel(), _stream(U.device)))
+    return RH, MG, F_col
 
 
 STATIC_K_MAX = 32

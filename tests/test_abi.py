@@ -66,8 +66,18 @@ def test_host_side_argument_errors(libpspec):
     assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, None, big, None, ctypes.byref(h)) == 1
     assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, ws + 8, big, None, ctypes.byref(h)) == 1
     assert b"aligned" in libpspec.pspec_last_error()
-    need = libpspec.pspec_graph_workspace_bytes(10, 5, 4)
-    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, ws, need - 1, None, ctypes.byref(h)) == 4
+    # below the counting part: refused before any device access (ws is not a device address)
+    libpspec.pspec_graph_count_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int]
+    libpspec.pspec_graph_count_workspace_bytes.restype = sz
+    fixed = libpspec.pspec_graph_count_workspace_bytes(10, 4)
+    assert 0 < fixed <= libpspec.pspec_graph_workspace_bytes(10, 5, 4) < libpspec.pspec_graph_workspace_bytes(10, 5000, 4)
+    assert libpspec.pspec_graph_create(10, 5, 1, 1, 1, 0, 4, ws, fixed - 1, None, ctypes.byref(h)) == 4
+    libpspec.pspec_graph_exact_workspace.argtypes = [ctypes.c_int64, ctypes.c_int64, vp, vp, ctypes.c_int, vp, sz,
+                                                     vp, ctypes.POINTER(sz)]
+    libpspec.pspec_graph_exact_workspace.restype = ctypes.c_int
+    need = sz()
+    assert libpspec.pspec_graph_exact_workspace(10, 5, 1, 1, 4, ws, fixed - 1, None, ctypes.byref(need)) == 4
+    assert libpspec.pspec_graph_exact_workspace(10, 5, 1, 1, 4, ws, fixed, None, None) == 1
     assert libpspec.pspec_graph_workspace_bytes(0, 5, 4) == 0 and libpspec.pspec_graph_workspace_bytes(10, 5, 65) == 0
     libpspec.pspec_objective.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, ctypes.c_double, vp, vp,
                                          vp]
@@ -147,8 +157,9 @@ def test_graph_workspace_bound_covers_every_schedule():
     assert f(n, nnz, 16) > base and f(n, 2 * nnz, 8) > base and f(2 * n, nnz, 8) > base
     # all rows of degree 33: 1000 heavy rows, 1000 chunks of 24 bytes; one row of degree 33000: 65 chunks,
     # all of them split chunks with 2 k_max doubles of scratch each
-    worst_chunks = max(n, -(-nnz // chunk))
-    assert base >= 24 * worst_chunks + 16 * worst_chunks + 2 * 8 * 8 * (-(-nnz // chunk))
+    # one row of degree 33000 cut at 8 segment boundaries: at most 65 + 8 chunks, all split chunks
+    worst_chunks = max(n, -(-nnz // chunk) + 8)
+    assert base >= 24 * worst_chunks + 2 * 8 * 8 * (-(-nnz // chunk) + 8)
     assert f(n, 0, 8) > 0  # an empty graph still needs its partial sums
 
 

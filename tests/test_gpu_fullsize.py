@@ -46,7 +46,18 @@ def test_fullsize_vs_oracle(name):
     RG2, MG2 = pspec.project(Ut, G)
     RH2, _ = pspec.project(Ut, HV, X=Vt, MX=MG2)
     assert torch.equal(RG, RG2) and torch.equal(MG, MG2) and torch.equal(RH, RH2)
-    del P, RH, RG, HV, G, RG2, RH2
+    # the fixed-U call of the truncated-CG loop: same MG and F_col, RH within the element-wise bound
+    # of rhvp's (the scale of G and HV carried through the two Gram products)
+    RH3, MG3, _ = pspec.rhess(dg, Ut, Vt, G, p, eps)
+    torch.cuda.synchronize()
+    assert torch.equal(MG, MG3)
+    Uh, Vh = Ut.double().cpu().numpy(), Vt.double().cpu().numpy()
+    aU, aV = np.abs(Uh), np.abs(Vh)
+    S_RH = SH + aU @ (aU.T @ SH) + aV @ (aU.T @ SG)
+    d = gu.ew(RH3.double().cpu().numpy(), RH.double().cpu().numpy(), S_RH)
+    print(f"{name}: rhess vs rhvp element-wise {d:.2e}", flush=True)
+    assert d <= 2 * gu.TOLS[torch.float32]["tau"]
+    del P, RH, RG, HV, G, RG2, RH2, RH3
     if name == "rmat22":
         assert info["heavy_rows"] > 0 and info["split_rows"] > 0
         HV, G, Fc = gu.gpu_hvp(dg, U, V, p, eps, torch.float32, layout="separate")

@@ -68,6 +68,21 @@ def _hub_graph():
     return g
 
 
+def expected_chunks(g, segs=8):
+    """The schedule's chunk count, recomputed: one chunk per row of LIGHT_MAX + 1 .. CHUNK edges; a
+    longer row is cut at the column-segment boundaries (bound[s] = first node j with
+    rowptr[j] >= ceil(s nnz / segs)) and every piece into chunks of at most CHUNK edges."""
+    L, C = pspec.LIGHT_MAX, pspec.CHUNK
+    deg = g.degrees()
+    bounds = [int(np.searchsorted(g.rowptr, (g.nnz * s + segs - 1) // segs, side="left")) for s in range(1, segs)]
+    total = int(np.sum((deg > L) & (deg <= C)))
+    for i in np.flatnonzero(deg > C):
+        cols = g.col[g.rowptr[i]:g.rowptr[i + 1]]
+        pos = [0] + [int(np.searchsorted(cols, b, side="left")) for b in bounds] + [len(cols)]
+        total += sum((pos[s + 1] - pos[s] + C - 1) // C for s in range(segs))
+    return total
+
+
 @pytest.mark.parametrize("k", [5, 32])
 def test_heavy_and_split_rows(k):
     print(f"[case] hubs k={k}", flush=True)
@@ -77,7 +92,7 @@ def test_heavy_and_split_rows(k):
     deg = g.degrees()
     assert info["heavy_rows"] == int(np.sum(deg > pspec.LIGHT_MAX))
     assert info["split_rows"] == int(np.sum(deg > pspec.CHUNK))
-    assert info["chunks"] == int(np.sum(np.where(deg > pspec.LIGHT_MAX, (deg + pspec.CHUNK - 1) // pspec.CHUNK, 0)))
+    assert info["chunks"] == expected_chunks(g)
     assert info["split_rows"] >= 2 and info["heavy_rows"] >= 5
     for dtype in (torch.float64, torch.float32):
         gu.check(gu.compare(g, k, 1.2, 1e-8, dtype, dg=dg), dtype)

@@ -110,3 +110,47 @@ def test_rhvp_rejects_bad_arguments():
     R = torch.empty_like(U)
     with pytest.raises(pspec.PSpecError):
         pspec.rhvp(dg, U, V, 1.5, 1e-8, RH=R, RG=R)  # outputs overlap each other
+
+
+@pytest.mark.parametrize("layout", ["separate", "interleaved"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("k", [3, 5, 16, 32, 64])
+def test_rhess_at_fixed_u_matches_rhvp_and_oracle(k, dtype, layout):
+    """pspec_rhess (U fixed, its gradient G given, no gradient rows or RG formed): MG and F_col equal
+    pspec_rhvp's bit for bit; RH agrees with pspec_rhvp's and with the oracle's Riemannian Hessian
+    entry by entry within tau times its forward-error scale (G's and HV's scales carried through the
+    projection), on the fused (16 <= k <= 32) and stand-alone paths."""
+    print(f"[case] rhess k={k} {dtype} {layout}", flush=True)
+    g = _GRAPHS["sbm20k"]()
+    Uh, Vh = _tangent_pair(g.n, k, seed=k)
+    dg = gu.device_graph(g, k)
+    U, V = _place(Uh, Vh, dtype, layout)
+    p, eps = 1.3, 1e-8
+    RH, RG, MG, Fc = pspec.rhvp(dg, U, V, p, eps)
+    G, _ = pspec.grad(dg, U, p)
+    RH2, MG2, Fc2 = pspec.rhess(dg, U, V, G, p, eps)
+    torch.cuda.synchronize()
+    assert torch.equal(MG, MG2) and torch.equal(Fc, Fc2)
+    Ur, Vr = U.double().cpu().numpy(), V.double().cpu().numpy()
+    HVo, Go, _ = gu.oracle_hvp(g, Ur, Vr, p, eps)
+    RHo = orc.riemannian_hessian(Ur, Go, HVo, Vr)
+    SG, SH = gu.oracle_scales(g, Ur, Vr, p, eps)
+    aU, aV = np.abs(Ur), np.abs(Vr)
+    S_RH = SH + aU @ (aU.T @ SH) + aV @ (aU.T @ SG)
+    tau = gu.TOLS[dtype]["tau"]
+    a, b = RH.double().cpu().numpy(), RH2.double().cpu().numpy()
+    e = dict(vs_oracle=gu.ew(b, RHo, S_RH), vs_rhvp=gu.ew(b, a, S_RH), rel=gu.rel(b, RHo))
+    print(e)
+    assert e["vs_oracle"] <= tau and e["vs_rhvp"] <= 2 * tau and e["rel"] <= gu.TOLS[dtype]["norm"], e
+
+
+def test_rhess_rejects_bad_arguments():
+    g = gen.sbm_bernoulli(1000, 4, 0.05, 0.002)
+    dg = gu.device_graph(g, 4)
+    U = torch.randn(g.n, 4, device="cuda")
+    V = torch.randn(g.n, 4, device="cuda")
+    G = torch.randn(g.n, 4, device="cuda")
+    with pytest.raises(pspec.PSpecError):
+        pspec.rhess(dg, U, V, G, 1.5, 1e-8, RH=G)  # output overlaps the given gradient
+    with pytest.raises(pspec.PSpecError):
+        pspec.rhess(dg, U, V, G[:500], 1.5, 1e-8)  # G of the wrong shape
