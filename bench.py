@@ -206,13 +206,14 @@ def summarize_pmc(workload: str, nnz: int, k: int, out_name: str, runs: list) ->
         if "TCC_HIT_sum" in cs and "TCC_MISS_sum" in cs:
             h, m = cs["TCC_HIT_sum"], cs["TCC_MISS_sum"]
             lines.append(f"L2 hit rate of `{nm}`: {h / max(h + m, 1):.3f} ({h:.4g} hits, {m:.4g} misses).")
-        if "SQ_INSTS_VALU_MFMA_MOPS_F64" in cs:
+        if cs.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) > 0:
             flops = cs["SQ_INSTS_VALU_MFMA_MOPS_F64"] * 512
             lines.append(f"FP64 matrix cores in `{nm}`: {flops / 1e9:.3g} GFLOP per dispatch (MOPS x 512), "
                          f"{flops / (ms[nm] * 1e-3) / 1e12:.2f} TFLOP/s = "
                          f"{flops / (ms[nm] * 1e-3) / 78.6e12:.1%} of the 78.6 TFLOP/s FP64 peak"
-                         + (f"; MFMA busy {cs['SQ_VALU_MFMA_BUSY_CYCLES'] / (CUS * CLOCK_HZ * ms[nm] * 1e-3):.1%} of "
-                            f"CU cycles." if "SQ_VALU_MFMA_BUSY_CYCLES" in cs else "."))
+                         + (f"; SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x CUs x cycles) = "
+                            f"{cs['SQ_VALU_MFMA_BUSY_CYCLES'] / (4 * CUS * CLOCK_HZ * ms[nm] * 1e-3):.1%}."
+                            if "SQ_VALU_MFMA_BUSY_CYCLES" in cs else "."))
     with open(os.path.join(PROFILES, f"{out_name}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
