@@ -28,7 +28,8 @@
  *          The library never allocates device memory: every buffer beyond the inputs and outputs
  *          is a workspace the caller passes in (sizes from the *_workspace_bytes functions).
  * Streams. Every call enqueues its kernels on `stream` and returns without synchronising, except
- *          pspec_graph_create (which synchronises `stream` once, see there).  `stream` may be NULL
+ *          pspec_graph_create and pspec_graph_exact_workspace (which synchronise `stream` twice,
+ *          see there).  `stream` may be NULL
  *          (the null stream).  A graph handle holds the scratch of its calls: at most one call per
  *          handle may be in flight at a time.
  * Types.   dt = PSPEC_F32: U/V/G/HV are float; edge arithmetic in FP32 (|x|^(p-2) as
@@ -90,18 +91,20 @@ typedef struct ihipEvent_t *pspec_event;
  *   and nnz stored entries.  With h = min(n, nnz / (PSPEC_LIGHT_MAX + 1)) possible heavy rows,
  *   s = min(n, nnz / (PSPEC_CHUNK + 1)) possible split rows and c = nnz / PSPEC_CHUNK + 8 s possible
  *   chunks of split rows, it is about
- *     24 (h + c) + 16 s + 16 k_max c + 32 k_max (n / 256 + 2048) + 8240 k_max + 96 n / 256   bytes
- *   (SBM n = 8M, nnz = 96M, k_max = 16: ~560 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32: ~1.3 GB).
+ *     24 (h + c) + 16 s + 16 k_max c + 32 k_max (n / 256 + 2048) + 8240 k_max + 8 n + 96 n / 256
+ *   bytes (SBM n = 8M, nnz = 96M, k_max = 16: ~630 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32:
+ *   ~1.4 GB).
  *   Returns 0 for arguments pspec_graph_create would reject (n < 1, nnz < 0, k_max outside
  *   1..PSPEC_K_MAX, n >= 2^31 - 1).
  *
  * pspec_graph_exact_workspace -- the exact size for one graph: validates the CSR and counts its
  *   schedule in `workspace` (device, 256-byte aligned, at least
- *   pspec_graph_count_workspace_bytes(n, k_max) bytes: the counters and partial sums, which depend
- *   on n and k_max only), writes the bytes pspec_graph_create needs for this graph to *needed (a
- *   host size_t) and synchronises `stream` once.  The same workspace, grown to *needed bytes, can
- *   then be passed to pspec_graph_create (SBM n = 8M, k_max = 16: ~23 MB; R-MAT-22, k_max = 32:
- *   ~210 MB).  Arguments and errors as for pspec_graph_create.
+ *   pspec_graph_count_workspace_bytes(n, k_max) bytes: the counters, row starts and partial sums,
+ *   which depend on n and k_max only), writes the bytes pspec_graph_create needs for this graph to
+ *   *needed (a host size_t) and synchronises `stream` twice (after validation, after counting).
+ *   The same workspace, grown to *needed bytes, can then be passed to pspec_graph_create (SBM
+ *   n = 8M, k_max = 16: ~87 MB; R-MAT-22, k_max = 32: ~244 MB).  Arguments and errors as for
+ *   pspec_graph_create.
  */
 size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max);
 size_t pspec_graph_count_workspace_bytes(int64_t n, int k_max);
@@ -120,8 +123,8 @@ pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *
  *                   (or at least the exact size pspec_graph_exact_workspace reports for this graph),
  *                   256-byte aligned, owned by the caller and BORROWED like the CSR (a smaller one
  *                   returns PSPEC_ERR_WORKSPACE).  Its contents need no initialisation.
- *   stream          the schedule is built on this stream; the call synchronises it once to read
- *                   back the sizes of the schedule.
+ *   stream          the schedule is built on this stream; the call synchronises it twice, after
+ *                   validating the CSR and to read back the sizes of the schedule.
  *   out             receives the handle (a small host object).
  * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
  * 16-lane group per row in node order; rows of up to PSPEC_CHUNK edges are one chunk each, handed
@@ -147,6 +150,10 @@ pspec_status pspec_graph_destroy(pspec_graph g);
 
 /* Schedule statistics: rows above PSPEC_LIGHT_MAX, chunks, rows spanning several chunks. */
 pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int64_t *chunks, int64_t *split_rows);
+
+/* *ascending (host int) = 1 if every row's columns are non-decreasing (checked at create), else 0.
+ * With ascending rows pspec_objective visits each undirected edge once (see there). */
+pspec_status pspec_graph_ascending(pspec_graph g, int *ascending);
 
 /*
  * pspec_rcm_order -- a locality relabelling of the graph for the edge pass (the vxm of Section 2
@@ -176,6 +183,11 @@ pspec_status pspec_graph_set_timing_events(pspec_graph g, pspec_event before, ps
  * w_ij |u_i^l - u_j^l|^p and D_l = ||u^l||_p^p; *F = sum_l F_col[l].
  *   U      n x k block (dt), leading dimension ldu.
  *   F_col  device, k doubles, may be NULL;  F  device, 1 double, may be NULL.
+ * When every row's columns ascend (pspec_graph_ascending), N_l is summed over the entries with
+ * j > i only, which for the symmetric graphs this library takes is the same sum (w and |x|^p are
+ * symmetric in i, j): half the gathers.  F_col then agrees with the F_col of the other calls to
+ * rounding, not bit for bit.  Otherwise every stored entry is visited and the result is bitwise
+ * that of pspec_grad / pspec_hvp.
  */
 pspec_status pspec_objective(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, double p,
                              double *F_col, double *F, pspec_stream stream);

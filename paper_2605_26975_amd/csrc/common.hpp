@@ -86,6 +86,10 @@ struct Graph {
     double *red1 = nullptr;       // device [kReduceSlices * kQ * k_max]
     double *scalars = nullptr;    // device [kScalars * k_max]
     double *chunk_scratch = nullptr;  // device [n_split_chunks * 2 * k_max] (row partials of split rows)
+    // Every row's columns ascend: then ustart[i] is the first position of row i holding a column
+    // above i, and the objective pass visits each undirected edge once (entries j > i only).
+    bool ascending = false;
+    const int64_t *ustart = nullptr;  // device [n]
     hipEvent_t ev_before = nullptr, ev_after = nullptr;  // optional edge-pass timing events
 };
 

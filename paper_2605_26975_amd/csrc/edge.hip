@@ -4,7 +4,9 @@
 //   N_l   = 1/2 sum w |x|^p                 numerator of Eq. (1)
 //   L_i   = sum_j w phi_p(x)                (Delta_p u)_i
 //   J_i   = sum_j w psi(x) (v_i - v_j)      (Hessian edge part / (p-1)), psi(x) = max(|x|, eps)^(p-2)
-// and per row: D_l += |u_i|^p, a_l += phi_p(u_i) v_i, S_l += L_i v_i.  One pass reads the CSR once
+// and per row: D_l += |u_i|^p, a_l += phi_p(u_i) v_i, S_l += L_i v_i.  The objective alone (OBJ) needs
+// no row output, so when every row's columns ascend it visits each undirected edge once: w and |x|^p
+// are symmetric in (i, j), hence N_l = sum over the entries j > i, half the gathers.  One pass reads the CSR once
 // and gathers the k contiguous values of u_j (and v_j) per edge from the row-major block; |x|^(p-2)
 // is formed once per edge-column as exp2((p-2) log2|x|) and gives phi = |x|^(p-2) x,
 // |x|^p = phi x and psi = min(|x|^(p-2), eps^(p-2)).
@@ -138,6 +140,8 @@ struct EdgeArgs {
     int64_t part_base; // first partial row of the chunks (= tiles)
     int64_t seg_base[kSegs + 1];  // chunks of column segment s: [seg_base[s], seg_base[s + 1])
     int64_t n_chunks;             // the shared list: [seg_base[kSegs], n_chunks)
+    const int64_t *ustart;        // OBJ over rows with ascending columns: the first entry j > i of each
+                                  // row (each undirected edge visited once); otherwise NULL
 };
 
 // One edge-column term.  wv is the weight (0 for padding lanes, whose gather is the row itself).
@@ -247,6 +251,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     constexpr int RS = kTileRows / NGRP;
     static_assert(kTileRows % NGRP == 0, "tile rows must split evenly over groups");
     __shared__ int64_t s_rp[kTileRows + 1];
+    __shared__ int64_t s_up[MODE == OBJ ? kTileRows : 1];
     __shared__ double s_red[kBlock / 64][kQ][K];
 
     const int tid = threadIdx.x;
@@ -263,8 +268,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     for (int t = tid; t <= kTileRows; t += kBlock) {
         const int64_t r = row0 + t;
         s_rp[t] = a.rowptr[r < a.n ? r : a.n];
+        if (MODE == OBJ && a.ustart != nullptr && t < kTileRows && r < a.n) s_up[t] = a.ustart[r];
     }
     __syncthreads();
+    // first entry of row rl this pass visits: the whole row, or its entries j > i (OBJ, ascending)
+    auto first = [&](int rl) -> int64_t {
+        if constexpr (MODE == OBJ) {
+            if (a.ustart != nullptr) return s_up[rl];
+        }
+        return s_rp[rl];
+    };
 
     const auto rU = make_rsrc(a.U, a.U_bytes);
     const auto rV = make_rsrc(a.V, a.V_bytes);
@@ -288,8 +301,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
         }
         r.wl = (T)0;
         if (valid) {
-            const int64_t b = s_rp[rl], d = s_rp[rl + 1] - b;
-            if (d <= a.light_max && gl < d) {
+            const int64_t b = first(rl), d = s_rp[rl + 1] - s_rp[rl];
+            if (d <= a.light_max && gl < s_rp[rl + 1] - b) {
                 j = (uint32_t)a.col[b + gl];
                 r.wl = (T)a.w[b + gl];
             }
@@ -308,8 +321,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
         const int rl = grp + s * NGRP;
         const int64_t row = row0 + rl;
         const bool valid = row < a.n;
-        const int64_t beg = valid ? s_rp[rl] : 0, end = valid ? s_rp[rl + 1] : 0;
-        const bool light = valid && (end - beg) <= a.light_max;
+        const int64_t beg = valid ? first(rl) : 0, end = valid ? s_rp[rl + 1] : 0;
+        const bool light = valid && (end - s_rp[rl]) <= a.light_max;
         const int64_t len = light ? end - beg : 0;
         const uint32_t own = valid ? (uint32_t)row : 0u;
         const RowPre cur = nxt;
@@ -448,14 +461,22 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
     double Nacc = 0.0, Sacc = 0.0;
     auto chunk = [&](int64_t ci) {
         const Chunk ch = a.chunks[ci];
-        const int len = (int)(ch.end - ch.beg);
+        int64_t cbeg = ch.beg;
+        if constexpr (MODE == OBJ) {
+            if (a.ustart != nullptr) {
+                const int64_t us = a.ustart[ch.row];
+                cbeg = us > cbeg ? us : cbeg;
+            }
+        }
+        const int len = ch.end > cbeg ? (int)(ch.end - cbeg) : 0;
+        if (MODE == OBJ && len == 0) return;  // no entry j > i in this chunk
         for (int t0 = 0; t0 < len; t0 += 4 * 64) {  // four ids per lane in flight
             uint32_t jj[4];
             WT ww[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int t = t0 + 64 * u + lane;
-                const int64_t src = ch.beg + (t < len ? t : len - 1);
+                const int64_t src = cbeg + (t < len ? t : len - 1);
                 jj[u] = (uint32_t)a.col[src];
                 ww[u] = a.w[src];
             }
@@ -608,7 +629,8 @@ __global__ __launch_bounds__(kBlock) void reduce_stage1(const double *__restrict
 // Stage 2 (one workgroup): totals and the per-column scalars.
 __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict__ red1, int W, int k, double p,
                                                       double *__restrict__ sc, int k_max, double *__restrict__ F_col,
-                                                      double *__restrict__ F, bool rank2, bool b_direct) {
+                                                      double *__restrict__ F, bool rank2, bool b_direct,
+                                                      double nscale) {
     __shared__ double s[kBlock];
     __shared__ double sf[PSPEC_K_MAX];
     const int tid = threadIdx.x;
@@ -619,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void reduce_stage2(const double *__restrict
     }
     __syncthreads();
     if (tid < k) {
-        const double N = 0.5 * s[0 * k + tid], D = s[1 * k + tid], av = s[2 * k + tid], S = s[3 * k + tid];
+        const double N = nscale * s[0 * k + tid], D = s[1 * k + tid], av = s[2 * k + tid], S = s[3 * k + tid];
         const double Fl = N / D, pD = p / D;
         sc[SC_N * k_max + tid] = N;
         sc[SC_D * k_max + tid] = D;
@@ -918,6 +940,7 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.part_base = g->tiles;
     for (int sg = 0; sg <= kSegs; ++sg) a.seg_base[sg] = g->seg_chunk_base[sg];
     a.n_chunks = g->n_chunks;
+    a.ustart = (MODE == OBJ && g->ascending) ? g->ustart : nullptr;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
     edge_light<T, WT, K, MODE, FLOOR><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     const int64_t hb = heavy_grid<T, WT, K>(g);
@@ -928,7 +951,9 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     if (g->ev_after) PSPEC_HIP(hipEventRecord(g->ev_after, s));
     const int W = kQ * k;
     reduce_stage1<<<kReduceSlices, kBlock, 0, s>>>(g->partials, g->tiles + hb, W, g->red1);
-    reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F, rank2, MODE == HESS);
+    // N = 1/2 sum over the stored entries, or the sum over the entries j > i
+    reduce_stage2<<<1, kBlock, 0, s>>>(g->red1, W, k, p, g->scalars, g->k_max, F_col, F, rank2, MODE == HESS,
+                                       a.ustart ? 1.0 : 0.5);
     return PSPEC_OK;
 }
 

@@ -73,6 +73,29 @@ __global__ __launch_bounds__(kBlock) void k_check_col(const int32_t *__restrict_
     if (bad) atomicOr(flag, 2);
 }
 
+// Upper parts of the rows, for the objective pass: one wave per row counts the entries with a column
+// at most i (ustart[i] = rowptr[i] + that count) and checks that the row's columns do not descend;
+// any descent sets bit 4 of *flag, and the objective pass then visits every stored entry instead.
+__global__ __launch_bounds__(kBlock) void k_upper(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                int64_t n, int64_t *__restrict__ ustart, int *__restrict__ flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < n; i += waves) {
+        const int64_t beg = rowptr[i], end = rowptr[i + 1];
+        int64_t low = 0;
+        for (int64_t q = beg + lane; q < end; q += 64) {
+            const int32_t c = col[q];
+            low += c <= (int32_t)i;
+            if (q + 1 < end && col[q + 1] < c) bad = 1;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
+        if (lane == 0) ustart[i] = beg + low;
+    }
+    if (__any(bad) && lane == 0) atomicOr(flag, 4);
+}
+
 // Column segment boundaries: bound[s] = the first node j with rowptr[j] >= s nnz / kSegs, so each
 // segment [bound[s], bound[s + 1]) holds an equal share of the stored entries -- and, the graph being
 // symmetric, receives an equal share of the neighbour gathers.  One thread per boundary.
@@ -247,7 +270,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restr
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Layout of the caller's workspace.  The first part depends on (n, k_max) only: the schedule kernels'
-// counters, the column-segment boundaries and the FP64 partial sums of the edge pass.  The schedule
+// counters, the column-segment boundaries, the rows' upper starts and the FP64 partial sums of the
+// edge pass.  The schedule
 // itself (chunk list, split-row list, split-row scratch) follows, sized by the counts of the graph:
 // exact once they are known, otherwise by bounds from (n, nnz) alone --
 //   heavy rows   <= min(n, nnz / (LIGHT_MAX + 1))      (each holds more than LIGHT_MAX edges)
@@ -256,7 +280,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   chunks       <= heavy rows + split chunks
 //   partial rows  = light tiles + kHeavyGridCap
 struct WsLayout {
-    size_t bcount = 0, tot = 0, bound = 0, part = 0, red1 = 0, sc = 0, chunks = 0, splits = 0, scr = 0;
+    size_t bcount = 0, tot = 0, bound = 0, ust = 0, part = 0, red1 = 0, sc = 0, chunks = 0, splits = 0, scr = 0;
     size_t fixed = 0, total = 0;
 };
 
@@ -268,6 +292,7 @@ WsLayout ws_layout(int64_t n, int k_max, int64_t n_chunks, int64_t n_split, int6
         align256(sizeof(int64_t) * (size_t)nb * kCounters),
         align256(sizeof(int64_t) * kCounters + sizeof(int)),
         align256(sizeof(int32_t) * (kSegs + 1)),
+        align256(sizeof(int64_t) * (size_t)n),
         align256(sizeof(double) * (size_t)(tiles + kHeavyGridCap) * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kReduceSlices * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kScalars * (size_t)k_max),
@@ -275,12 +300,12 @@ WsLayout ws_layout(int64_t n, int k_max, int64_t n_chunks, int64_t n_split, int6
         align256(sizeof(Split) * (size_t)n_split),
         align256(sizeof(double) * (size_t)n_split_chunks * 2 * (size_t)k_max),
     };
-    size_t *dst[] = {&L.bcount, &L.tot, &L.bound, &L.part, &L.red1, &L.sc, &L.chunks, &L.splits, &L.scr};
+    size_t *dst[] = {&L.bcount, &L.tot, &L.bound, &L.ust, &L.part, &L.red1, &L.sc, &L.chunks, &L.splits, &L.scr};
     size_t off = 0;
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < 10; ++i) {
         *dst[i] = off;
         off += parts[i];
-        if (i == 5) L.fixed = off;
+        if (i == 6) L.fixed = off;
     }
     L.total = off;
     return L;
@@ -300,11 +325,13 @@ bool ws_args_ok(int64_t n, int64_t nnz, int k_max) {
 // The counts of a graph's schedule (validated CSR): tot[kCounters] from the counting kernels.
 struct Plan {
     int64_t tot[kCounters];
+    int flag = 0;  // bit 4: some row's columns descend
     int64_t n_chunks() const { return tot[kCGlob] + tot[kCSplitChunks]; }
 };
 
 // Shared front half of create and the workspace query: argument checks, CSR validation, segment
-// boundaries and schedule counts in the workspace's fixed part; synchronises the stream once.
+// boundaries, upper starts and schedule counts in the workspace's fixed part; synchronises the
+// stream twice.
 pspec_status plan_counts(const char *who, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col, int k_max,
                          void *workspace, size_t ws_bytes, hipStream_t s, WsLayout &L, Plan &plan) {
     PSPEC_ARG(n >= 1, "%s: n = %lld < 1", who, (long long)n);
@@ -341,12 +368,18 @@ pspec_status plan_counts(const char *who, int64_t n, int64_t nnz, const int64_t 
                   (host_flag & 2) ? " column indices out of range" : "");
         return PSPEC_ERR_ARG;
     }
-    // only a validated CSR is searched: the boundaries and the counts read rowptr and col
+    // only a validated CSR is searched: the boundaries, upper starts and counts read rowptr and col
     k_seg_bounds<<<1, 64, 0, s>>>(rowptr, n, nnz, bound);
+    {
+        const int64_t want = (n + kBlock / 64 - 1) / (kBlock / 64);
+        k_upper<<<(unsigned)(want < 65536 ? want : 65536), kBlock, 0, s>>>(
+            rowptr, col, n, reinterpret_cast<int64_t *>(mem + L.ust), flag);
+    }
     k_plan_count<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, bound, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount);
     k_plan_scan<<<1, kPlanBlock, 0, s>>>(bcount, nb, tot);
     PSPEC_HIP(hipGetLastError());
     PSPEC_HIP(hipMemcpyAsync(plan.tot, tot, sizeof(int64_t) * kCounters, hipMemcpyDeviceToHost, s));
+    PSPEC_HIP(hipMemcpyAsync(&plan.flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     PSPEC_HIP(hipStreamSynchronize(s));
     // the bounds of ws_bound hold for every valid CSR; a violation means the counts are wrong
     const WsLayout B = ws_bound(n, nnz, k_max);
@@ -442,6 +475,8 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->red1 = reinterpret_cast<double *>(mem + L.red1);
     g->scalars = reinterpret_cast<double *>(mem + L.sc);
     g->chunk_scratch = reinterpret_cast<double *>(mem + L.scr);
+    g->ascending = (plan.flag & 4) == 0;
+    g->ustart = reinterpret_cast<const int64_t *>(mem + L.ust);
     if (g->n_chunks > 0) {
         const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
         k_plan_emit<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, reinterpret_cast<const int32_t *>(mem + L.bound),
@@ -471,6 +506,14 @@ extern "C" pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int
     if (heavy_rows) *heavy_rows = g->heavy_rows;
     if (chunks) *chunks = g->n_chunks;
     if (split_rows) *split_rows = g->n_split;
+    return PSPEC_OK;
+}
+
+extern "C" pspec_status pspec_graph_ascending(pspec_graph g, int *ascending) {
+    clear_error();
+    PSPEC_ARG(g != nullptr, "graph_ascending: NULL handle");
+    PSPEC_ARG(ascending != nullptr, "graph_ascending: ascending is NULL");
+    *ascending = g->ascending ? 1 : 0;
     return PSPEC_OK;
 }
 

@@ -69,6 +69,14 @@ def inputs(n, k, seed_u=gen.SEED_U, seed_v=gen.SEED_V):
     return U, V
 
 
+def shuffled(g, seed=5):
+    """The same graph with each row's entries in a seeded random order (columns no longer ascend)."""
+    rng = np.random.default_rng(seed)
+    key = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.rowptr)) * 2.0 + rng.random(g.nnz)
+    order = np.argsort(key, kind="stable")
+    return gen.Graph(g.n, g.rowptr.copy(), g.col[order].copy(), g.w[order].copy(), name=g.name + "-shuffled")
+
+
 def device_graph(g, k_max, weight_dtype=torch.float32):
     return pspec.Graph.from_host(g, "cuda", k_max=k_max, weight_dtype=weight_dtype)
 
@@ -118,8 +126,9 @@ def errors(HVg, Gg, Fcg, HVo, Go, Fco, SG, SH) -> dict:
 
 
 def compare(g, k, p, eps, dtype, U=None, V=None, dg=None, layout="separate"):
-    """Errors of the GPU path against the oracle (see errors(); plus F of pspec_objective and
-    whether its F_col equals the HVP call's bit for bit)."""
+    """Errors of the GPU path against the oracle (see errors(); plus F and F_col of pspec_objective,
+    which on graphs with ascending rows sums each undirected edge once and so agrees with the HVP
+    call's F_col to rounding only)."""
     if U is None:
         U, V = inputs(g.n, k)
     if dg is None:
@@ -130,7 +139,7 @@ def compare(g, k, p, eps, dtype, U=None, V=None, dg=None, layout="separate"):
     Fg, Fcg2 = gpu_objective(dg, U, p, dtype)
     err = errors(HVg, Gg, Fcg, HVo, Go, Fco, SG, SH)
     err["F"] = abs(Fg - Fco.sum()) / abs(Fco.sum())
-    err["objective_matches_hvp"] = bool(np.array_equal(Fcg, Fcg2))
+    err["Fcol_obj"] = float(np.max(np.abs(Fcg2 - Fco) / np.abs(Fco))) if Fco.size else 0.0
     return err
 
 
@@ -140,7 +149,7 @@ def check(e: dict, dtype, norms=True) -> None:
     where G is a difference of nearly equal terms and its norm says nothing about the arithmetic)."""
     t = TOLS[dtype]
     print({k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()}, flush=True)
-    assert e.get("F", 0.0) <= t["F"] and e["Fcol"] <= t["F"], e
+    assert e.get("F", 0.0) <= t["F"] and e["Fcol"] <= t["F"] and e.get("Fcol_obj", 0.0) <= t["F"], e
     if norms:
         assert e["G"] <= t["norm"] and e["G_colmax"] <= t["norm"], e
         assert e["HV"] <= t["norm"] and e["HV_colmax"] <= t["norm"], e

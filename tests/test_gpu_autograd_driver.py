@@ -20,7 +20,8 @@ def grid128():
 def _away_from_kinks(g, U, V, delta=1e-2):
     """V with zeros wherever a central difference along V could cross a kink of |x|^(p-1) or
     |u|^(p-1): at both ends of every edge with |u_i - u_j| < delta and where |u_i| < delta, per
-    column.  With |h V| <= 1e-5 the differences then stay >= 1e3 |h (v_i - v_j)| from every kink.
+    column.  Along h V every edge difference and entry then stays at least delta - 2 h max|V| from
+    its kink (h <= 1e-4, max|V| ~ 6: at least 8.8e-3, eight times the step).
     Returns the masked V and the number of zeroed entries."""
     rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
     near = np.abs(U[rows] - U[g.col]) < delta
@@ -32,7 +33,7 @@ def _away_from_kinks(g, U, V, delta=1e-2):
 
 def test_autograd_gradient_vs_oracle_and_fd(grid128):
     g = grid128
-    k, p, eps, h = 8, 1.2, 1e-8, 1e-6
+    k, p, eps = 8, 1.2, 1e-8
     print(f"[case] grid128 autograd k={k} p={p}", flush=True)
     U, V = gu.inputs(g.n, k)
     dg = gu.device_graph(g, k)
@@ -46,7 +47,12 @@ def test_autograd_gradient_vs_oracle_and_fd(grid128):
     assert gu.rel(G32h, Go) < 1e-5 and gu.colmax(G32h, Go) < 1e-5
     assert gu.ew(G32h, Go, SG) <= gu.TOLS[torch.float32]["tau"]
     assert abs(float(F32.detach()) - Fco.sum()) / Fco.sum() < 1e-5
-    # FP64 path: directional derivative against a central difference of F
+    # FP64 path: directional derivative against a central difference of F.  F (~36) is a sum of
+    # 12.5M terms whose FP64 rounding noise, ~1e-13 of F, the difference divides by 2 hF: at
+    # hF = 1e-4 that is ~2e-8 against a derivative of ~7e-4, and the O(hF^2) truncation (every
+    # difference stays >= 8.8e-3 from a kink) is smaller still; at 1e-6 the noise alone would be
+    # ~3e-5 of the derivative.
+    hF = 1e-4
     Vm, zeroed = _away_from_kinks(g, U, V)
     print(f"direction zeroed at {zeroed} of {V.size} entries near kinks")
     assert zeroed < 0.05 * V.size
@@ -55,11 +61,11 @@ def test_autograd_gradient_vs_oracle_and_fd(grid128):
     F64 = pag.objective(U64, dg, p, eps)
     (G64,) = torch.autograd.grad(F64, U64, create_graph=True)
     with torch.no_grad():
-        Fp = float(pag.objective(U64 + h * V64, dg, p, eps))
-        Fm = float(pag.objective(U64 - h * V64, dg, p, eps))
-    fd = (Fp - Fm) / (2 * h)
+        Fp = float(pag.objective(U64 + hF * V64, dg, p, eps))
+        Fm = float(pag.objective(U64 - hF * V64, dg, p, eps))
+    fd = (Fp - Fm) / (2 * hF)
     an = float((G64 * V64).sum())
-    assert abs(an - fd) <= 1e-6 * abs(fd), (an, fd)
+    assert abs(an - fd) <= 1e-4 * abs(fd), (an, fd)
 
 
 def test_autograd_hvp_vs_fd_and_forward_mode(grid128):
