@@ -76,12 +76,13 @@ def _short(name: str) -> str:
 
 
 def is_edge_pass_kernel(name: str, k: int) -> bool:
-    """The kernels of the FP32 grad+HVP edge pass at width k: light rows, heavy chunks, split-row
-    combine (not the gather-floor reference, whose last template argument is true)."""
+    """The kernels of the FP32 grad+HVP edge pass at width k: light rows (at 9 <= k <= 16 with the
+    Gram products), heavy chunks, split-row combine (not the gather-floor reference, whose FLOOR
+    template argument is true)."""
     nm, K = _short(name), _pad_k(k)
-    return (nm == f"edge_light<float, float, {K}, 2, false>" or
-            (nm.startswith(f"edge_heavy<float, float, {K}, 2, ") and nm.endswith(", false>")) or
-            nm == "combine_split<float, 2>")
+    return (nm in (f"edge_light<float, float, {K}, 2, false, false>", f"edge_light<float, float, {K}, 2, false, true>")
+            or (nm.startswith(f"edge_heavy<float, float, {K}, 2, ") and nm.endswith(", false>"))
+            or nm == "combine_split<float, 2>")
 
 
 def _stored(kind: str, workload: str, layout: str):
@@ -156,7 +157,8 @@ def summarize_pmc(workload: str, nnz: int, k: int, out_name: str, runs: list) ->
             med.setdefault(nm, {}).update(cs)
             ms[nm] = t[nm]
     edge = [nm for nm in med if is_edge_pass_kernel(nm, k)]
-    gram = [nm for nm in med if nm.startswith(("finalize_gram", "apply_rhvp", "gram_partial", "apply_rows"))]
+    gram = [nm for nm in med if nm.startswith(("finalize_gram", "gram_heavy", "sum_range", "apply_rhvp",
+                                               "gram_partial", "apply_rows"))]
     copy = [nm for nm in med if nm.startswith("axpby_k<float, 16, true>")]
     layout, lines = "interleaved", []
     lines += [f"# Counters: {workload} (nnz = {nnz}, k = {k}), FP32", "",
@@ -562,6 +564,9 @@ def main() -> int:
             "step": ("rhvp (grad, HVP, both Grassmann projections)" if args.step == "fused" else
                      "hvp (fused grad) + 2x project") + " + retract + objective",
             "edge_col_updates_per_step": nnz * k,
+            # row schedule of the graph handle; with ascending rows the objective pass visits each
+            # undirected edge once
+            "schedule": dg.info(),
         },
         "roofline": {
             "bound": "hbm",
@@ -570,7 +575,8 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "fused grad+HVP edge pass (light rows, heavy chunks, split-row combine)",
+            "kernel": ("fused grad+HVP edge pass (light rows, heavy chunks, split-row combine; "
+                       "at 9 <= k <= 16 the light rows also form the Gram products of the projection)"),
             "algorithmic_bytes_per_launch": alg_bytes,
             "launch_ms": edge_ms,
             "valu": None if args.permute else stored_valu(args.workload, args.layout, edge_ms),

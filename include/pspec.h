@@ -92,8 +92,10 @@ typedef struct ihipEvent_t *pspec_event;
  *   s = min(n, nnz / (PSPEC_CHUNK + 1)) possible split rows and c = nnz / PSPEC_CHUNK + 8 s possible
  *   chunks of split rows, it is about
  *     24 (h + c) + 16 s + 16 k_max c + 32 k_max (n / 256 + 2048) + 8240 k_max + 8 n + 96 n / 256
- *   bytes (SBM n = 8M, nnz = 96M, k_max = 16: ~630 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32:
- *   ~1.4 GB).
+ *       + (k_max > 8 ? 8192 (n / 256 + 1313) : 0)
+ *   bytes (SBM n = 8M, nnz = 96M, k_max = 16: ~900 MB; R-MAT n = 4.2M, nnz = 128M, k_max = 32:
+ *   ~1.5 GB).  The last term holds the FP64 Gram partials of pspec_rhvp / pspec_rhess at
+ *   9 <= k <= 16 in FP32, formed inside the edge pass (one 4 x k x k partial per 256 rows).
  *   Returns 0 for arguments pspec_graph_create would reject (n < 1, nnz < 0, k_max outside
  *   1..PSPEC_K_MAX, n >= 2^31 - 1).
  *
@@ -103,7 +105,7 @@ typedef struct ihipEvent_t *pspec_event;
  *   which depend on n and k_max only), writes the bytes pspec_graph_create needs for this graph to
  *   *needed (a host size_t) and synchronises `stream` twice (after validation, after counting).
  *   The same workspace, grown to *needed bytes, can then be passed to pspec_graph_create (SBM
- *   n = 8M, k_max = 16: ~87 MB; R-MAT-22, k_max = 32: ~244 MB).  Arguments and errors as for
+ *   n = 8M, k_max = 16: ~355 MB; R-MAT-22, k_max = 32: ~380 MB).  Arguments and errors as for
  *   pspec_graph_create.
  */
 size_t pspec_graph_workspace_bytes(int64_t n, int64_t nnz, int k_max);
@@ -281,9 +283,13 @@ pspec_status pspec_retract(int64_t n, int k, pspec_dtype dt, const void *U, int6
  *   MG = U^T G                                   (k x k, FP64, row-major, written if MG != NULL)
  *   RG = G - U MG                                (Riemannian gradient P_U(G))
  *   RH = HV - U (U^T HV) - V MG                  (Riemannian Hessian P_U(H V) - V (U^T G))
- * where G and HV are the outputs of pspec_hvp.  The results are bit-identical to pspec_hvp
- * followed by pspec_project(U, G) and pspec_project(U, HV, X = V, MX = MG); the epilogue, the two
- * Gram matrices and both projections share passes over the rows, and G and HV are never written.
+ * where G and HV are the outputs of pspec_hvp.  G and HV are never written: in FP32 at
+ * 9 <= k <= 16 the edge pass itself forms the Gram products U^T (Delta_p u), U^T J, U^T phi_p(u)
+ * and U^T (psi(u) v) on the matrix cores, row by row as it finishes them, and MG and U^T HV are
+ * combined from these in FP64 (no pass over the rows between the edge pass and the projection);
+ * the results then agree with pspec_hvp followed by pspec_project(U, G) and
+ * pspec_project(U, HV, X = V, MX = MG) to rounding.  Otherwise one pass forms the epilogue and both
+ * Gram matrices and the results are bit-identical to that sequence.
  *   V       n x k tangent direction (dt), leading dimension ldv (may be U + k with ldu = ldv).
  *   RH, RG  n x k outputs (dt); both REQUIRED; neither may overlap U, V or each other.
  *   F_col   device, k doubles (the objective per column), may be NULL.
@@ -304,8 +310,9 @@ pspec_status pspec_rhvp(pspec_graph g, pspec_dtype dt, int k, const void *U, int
  * with pspec_rhvp the edge pass forms no (Delta_p u) rows and writes none, g^T v is summed from G
  * directly, and RG is not formed or written: one n x k row block less written per call on each side
  * (SBM n = 8M, k = 16: 1 GB of the ~20 GB a pspec_rhvp call moves).  RH agrees with pspec_rhvp's
- * to rounding (b = g^T v is summed from the rounded G instead of from (Delta_p u)^T v), F_col and MG
- * bit for bit.  V, RH, ws, F_col, layout and errors as for pspec_rhvp; RH must not overlap U, V or
+ * to rounding (b = g^T v is summed from the rounded G instead of from (Delta_p u)^T v), F_col bit
+ * for bit, MG bit for bit unless the Gram products are formed in the edge pass (FP32,
+ * 9 <= k <= 16: then to rounding).  V, RH, ws, F_col, layout and errors as for pspec_rhvp; RH must not overlap U, V or
  * G.
  */
 pspec_status pspec_rhess(pspec_graph g, pspec_dtype dt, int k, const void *U, int64_t ldu, const void *V,

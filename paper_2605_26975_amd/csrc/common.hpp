@@ -62,6 +62,15 @@ constexpr int kTileRows = 256;     // rows per light-kernel workgroup (one FP64 
 constexpr int kQ = 4;              // FP64 partial sums per column: N, D, a = phi^T v, S_L = L^T v
 constexpr int kReduceSlices = 256; // first-stage workgroups of the deterministic reduction
 constexpr int kScalars = 6;        // per-column scalars kept on the device (see Sc below)
+// Gram products of the Riemannian call at 9 <= k <= 16, formed in the edge pass: kGramQ k x k FP64 partials
+// per light tile and per workgroup (at most kGramHeavyBlocks) over the heavy rows, summed in fixed
+// order through kGramMid and kGramMid / 32 intermediate rows to one.
+constexpr int kGramQ = 4;
+constexpr int kGramK = 16;
+constexpr int kGramHeavyBlocks = 256;
+constexpr int kGramMid = 1024;
+// Rows of kGramQ * kGramK^2 doubles in the Gram area of a graph with `tiles` light tiles.
+inline int64_t gram_area_rows(int64_t tiles) { return tiles + kGramHeavyBlocks + kGramMid + kGramMid / 32 + 1; }
 
 // Index of each per-column scalar in Graph::scalars ([kScalars][k_max]).
 enum Sc { SC_N = 0, SC_D = 1, SC_F = 2, SC_PD = 3, SC_A = 4, SC_B = 5 };
@@ -90,6 +99,7 @@ struct Graph {
     // above i, and the objective pass visits each undirected edge once (entries j > i only).
     bool ascending = false;
     const int64_t *ustart = nullptr;  // device [n]
+    double *gram_part = nullptr;      // device [gram_area_rows(tiles)][kGramQ * kGramK^2] (k_max > 8), else NULL
     hipEvent_t ev_before = nullptr, ev_after = nullptr;  // optional edge-pass timing events
 };
 

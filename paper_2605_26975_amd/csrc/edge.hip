@@ -142,6 +142,7 @@ struct EdgeArgs {
     int64_t n_chunks;             // the shared list: [seg_base[kSegs], n_chunks)
     const int64_t *ustart;        // OBJ over rows with ascending columns: the first entry j > i of each
                                   // row (each undirected edge visited once); otherwise NULL
+    double *gpart;                // light kernel with Gram products: [tiles][kGramQ][k][k]
 };
 
 // One edge-column term.  wv is the weight (0 for padding lanes, whose gather is the row itself).
@@ -235,13 +236,13 @@ constexpr int light_cpl() {
 }
 
 // Waves per SIMD the light kernel is compiled for (k = 32 in FP32 sits just above 128 VGPRs).
-template <typename T, int K>
+template <typename T, int K, bool GRAM = false>
 constexpr int light_waves() {
-    return (sizeof(T) == 4 && K == 32) ? 4 : 1;
+    return GRAM ? 4 : (sizeof(T) == 4 && K == 32) ? 4 : 1;
 }
 
-template <typename T, typename WT, int K, int MODE, bool FLOOR = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_waves<T, K>()))) void edge_light(EdgeArgs<T, WT> a) {
+template <typename T, typename WT, int K, int MODE, bool FLOOR = false, bool GRAM = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_waves<T, K, GRAM>()))) void edge_light(EdgeArgs<T, WT> a) {
     constexpr int G = 16;
     constexpr int CPL = light_cpl<K>();  // columns per lane
     constexpr int KL = K / CPL;          // column lanes per edge slot
@@ -253,6 +254,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     __shared__ int64_t s_rp[kTileRows + 1];
     __shared__ int64_t s_up[MODE == OBJ ? kTileRows : 1];
     __shared__ double s_red[kBlock / 64][kQ][K];
+    __shared__ double s_gred[GRAM ? kBlock / 64 : 1][4][64];
+    static_assert(!GRAM || (K == 16 && (MODE == HVP || MODE == HESS) && !FLOOR), "Gram products: k = 16, HVP or HESS");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -317,6 +320,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     for (int i = 0; i < kQ; ++i)
 #pragma unroll
         for (int m = 0; m < CPL; ++m) q[i][m] = 0.0;
+    // GRAM: the four products U^T X of this wave's rows on the matrix cores, X = L (HVP) or the given
+    // gradient (HESS), J, phi_p(u), psi(u) v.  Lane 16 q + c holds column c of row q of the wave's four
+    // rows, which is the operand layout of v_mfma_f64_16x16x4f64 (A[c][q] = u, B[q][c] = x).
+    dbl4 gacc[GRAM ? kGramQ : 1];
+#pragma unroll
+    for (int i = 0; i < (GRAM ? kGramQ : 1); ++i) gacc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < RS; ++s) {
         const int rl = grp + s * NGRP;
         const int64_t row = row0 + rl;
@@ -391,17 +400,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                 }
             }
             q[0][m] += (double)Ns[m];
+            const T ui = cur.ui[m], vi = cur.vi[m];
+            const T hi = a.pw(fabs(ui));
+            const T phi = hi * ui;  // phi_p(u_i)
+            // HESS: g_i read here (not held through the row); own is row 0 past the last row
+            const T gi = MODE == HESS ? bload<T>(rG, own * a.ldg_b + cb[m]) : T(0);
+            if constexpr (GRAM) {
+                const double A = (light && c < a.k) ? (double)ui : 0.0;
+                gacc[0] = mfma_f64(A, MODE == HESS ? (double)gi : (double)Ls[m], gacc[0]);
+                gacc[1] = mfma_f64(A, (double)Js[m], gacc[1]);
+                gacc[2] = mfma_f64(A, (double)phi, gacc[2]);
+                gacc[3] = mfma_f64(A, (double)(fmin(hi, a.epsc) * vi), gacc[3]);
+            }
             if (valid && e == 0) {
-                const T ui = cur.ui[m], vi = cur.vi[m];
-                const T hi = a.pw(fabs(ui));
-                const T phi = hi * ui;  // phi_p(u_i)
                 q[1][m] += (double)(phi * ui);
                 if (mode_v(MODE)) q[2][m] += (double)phi * (double)vi;
                 if (MODE == HVP && light) q[3][m] += (double)Ls[m] * (double)vi;
-                if (MODE == HESS) {  // g^T v over every row, g_i read here (not held through the row)
-                    const T gi = bload<T>(rG, (uint32_t)row * a.ldg_b + cb[m]);
-                    q[3][m] += (double)gi * (double)vi;
-                }
+                if (MODE == HESS) q[3][m] += (double)gi * (double)vi;  // g^T v over every row
                 const int cm = c + m * KL;
                 if (light && cm < a.k) {
                     if (mode_l(MODE)) a.L[row * a.ldl + cm] = Ls[m];
@@ -431,6 +446,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
 #pragma unroll
         for (int wv = 0; wv < kBlock / 64; ++wv) sum += s_red[wv][i][cc];
         if (cc < a.k) prow[i * a.k + cc] = sum;
+    }
+    if constexpr (GRAM) {  // the four waves' products added in wave order: one partial per tile
+        dbl4 acc[kGramQ][1][1];
+#pragma unroll
+        for (int i = 0; i < kGramQ; ++i) acc[i][0][0] = gacc[i];
+        gram_mfma_reduce<16, kGramQ>(acc, s_gred, a.k, a.gpart + (int64_t)blockIdx.x * kGramQ * a.k * a.k);
     }
 }
 
@@ -907,7 +928,7 @@ unsigned grid_for(int64_t items, int64_t per_block, int64_t cap) {
 
 // The edge pass proper: edge kernels, split-row combine and the reductions to the per-column
 // scalars; L and J receive the raw rows.
-template <typename T, typename WT, int K, int MODE, bool FLOOR = false>
+template <typename T, typename WT, int K, int MODE, bool FLOOR = false, bool GRAM = false>
 pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int64_t ldv, T *L, int64_t ldl, T *J, int64_t ldj,
                double p, double eps, double *F_col, double *F, hipStream_t s, bool rank2 = true,
                const T *Gc = nullptr, int64_t ldgc = 0) {
@@ -941,8 +962,9 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     for (int sg = 0; sg <= kSegs; ++sg) a.seg_base[sg] = g->seg_chunk_base[sg];
     a.n_chunks = g->n_chunks;
     a.ustart = (MODE == OBJ && g->ascending) ? g->ustart : nullptr;
+    a.gpart = GRAM ? g->gram_part : nullptr;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
-    edge_light<T, WT, K, MODE, FLOOR><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
+    edge_light<T, WT, K, MODE, FLOOR, GRAM><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     const int64_t hb = heavy_grid<T, WT, K>(g);
     if (hb > 0) edge_heavy<T, WT, K, MODE, heavy_unroll<T, K>(), FLOOR><<<(unsigned)hb, kBlock, 0, s>>>(a);
     if (g->n_split > 0 && MODE != OBJ)
@@ -982,6 +1004,99 @@ constexpr bool rhvp_fused() {
     return K >= 16 && K <= 32;
 }
 
+// Gram products of the heavy rows (more than PSPEC_LIGHT_MAX entries), which the light kernel leaves
+// out: the same four products U^T X, U^T J, U^T phi_p(u), U^T (psi(u) v) over the rows of the shared
+// chunk list (one chunk each) and of the split-row list, after the split rows are combined; X is L
+// (HVP) or the given gradient (HESS).  Workgroup b takes a contiguous range of that row list.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void gram_heavy(const Chunk *__restrict__ glob, int64_t n_glob,
+                                                   const Split *__restrict__ splits, int64_t n_split, int k,
+                                                   const T *__restrict__ U, int64_t ldu, const T *__restrict__ V,
+                                                   int64_t ldv, const T *__restrict__ X, int64_t ldx,
+                                                   const T *__restrict__ J, int64_t ldj, PowM2<T> pw, T epsc,
+                                                   double *__restrict__ part) {
+    __shared__ double s_red[4][4][64];
+    int64_t r0, r1;
+    block_rows(n_glob + n_split, r0, r1);
+    auto row_of = [&](int64_t h) -> int64_t { return h < n_glob ? (int64_t)glob[h].row : (int64_t)splits[h - n_glob].row; };
+    struct Raw {
+        T u, v, x, j;
+        __device__ void pin() {
+            pspec::pin(u);
+            pspec::pin(v);
+            pspec::pin(x);
+            pspec::pin(j);
+        }
+    };
+    auto load = [&](int64_t h, int cl, Raw &raw) {
+        const int64_t r = row_of(h < r1 ? h : r1 - 1);
+        const int col = cl < k ? cl : k - 1;
+        raw.u = U[r * ldu + col];
+        raw.v = V[r * ldv + col];
+        raw.x = X[r * ldx + col];
+        raw.j = J[r * ldj + col];
+    };
+    auto finish = [&](int64_t h, int cl, const Raw &raw, T(&av)[1], T(&bv)[kGramQ][1]) {
+        const T hi = pw(fabs(raw.u));
+        av[0] = (h < r1 && cl < k) ? raw.u : T(0);
+        bv[0][0] = raw.x;
+        bv[1][0] = raw.j;
+        bv[2][0] = hi * raw.u;
+        bv[3][0] = fmin(hi, epsc) * raw.v;
+    };
+    dbl4 acc[kGramQ][1][1];
+#pragma unroll
+    for (int i = 0; i < kGramQ; ++i) acc[i][0][0] = dbl4{0.0, 0.0, 0.0, 0.0};
+    gram_mfma_rows<T, 16, kGramQ, 4, Raw>(r0, r1, load, finish, acc);
+    gram_mfma_reduce<16, kGramQ>(acc, s_red, k, part + (int64_t)blockIdx.x * kGramQ * k * k);
+}
+
+// out[g][e] = sum of part[q][e] over the contiguous range of q that group g = blockIdx.y of `groups`
+// takes (rows of `len` doubles), in q order.
+__global__ __launch_bounds__(kBlock) void sum_range(const double *__restrict__ part, int64_t P, int len, int groups,
+                                                  double *__restrict__ out) {
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= len) return;
+    const int64_t per = (P + groups - 1) / groups;
+    const int64_t q0 = (int64_t)blockIdx.y * per, q1 = q0 + per < P ? q0 + per : P;
+    double acc = 0.0;
+    int64_t q = q0;
+    for (; q + 8 <= q1; q += 8) {  // eight loads in flight, added in q order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(q + u) * len + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; q < q1; ++q) acc += part[q * len + e];
+    out[(int64_t)blockIdx.y * len + e] = acc;
+}
+
+// MG = U^T G and MH = U^T HV from the four Gram products (U^T X, U^T J, U^T phi, U^T (psi v)) and the
+// per-column scalars, following the epilogue term by term: column l of G is (p/D)(L - F phi) (or the
+// given gradient in HESS mode) and column l of HV is (p/D)((p-1) J - F (p-1) psi v - g a - phi b).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void gram_combine(const double *__restrict__ fin, int k, double p,
+                                                     const double *__restrict__ sc, int k_max,
+                                                     double *__restrict__ MG, double *__restrict__ MH,
+                                                     double *__restrict__ MG_out) {
+    const int kk = k * k;
+    for (int t = threadIdx.x; t < kk; t += kBlock) {
+        const ColScalars s = col_scalars(sc, k_max, t % k);
+        const double GX = fin[t], GJ = fin[kk + t], GP = fin[2 * kk + t], GS = fin[3 * kk + t];
+        const double mg = MODE == HESS ? GX : s.pD * (GX - s.F * GP);
+        MG[t] = mg;
+        MH[t] = s.pD * ((p - 1.0) * GJ - s.F * (p - 1.0) * GS - mg * s.a - GP * s.b);
+        if (MG_out) MG_out[t] = mg;
+    }
+}
+
+// Whether the Riemannian call forms its Gram products inside the edge pass (FP32, 9 <= k <= 16).
+template <typename T, int K>
+constexpr bool rhvp_gram_in_edge() {
+    return sizeof(T) == 4 && K == kGramK;
+}
+
 // Riemannian gradient and Hessian-vector product on Gr(k, n).  Workspace: level-1 partials
 // [kDenseBlocks][2][k*k], level-2 partials, then MG = U^T G and MH = U^T HV (k*k each).
 // MODE = HVP: RG and RH from U and V.  MODE = HESS: RH only, at a U whose Euclidean gradient is given
@@ -997,12 +1112,37 @@ pspec_status launch_rhvp(Graph *g, int k, const T *U, int64_t ldu, const T *V, i
     PowM2<T> pw;
     pw.pm2 = (T)(p - 2.0);
     const T epsc = (T)std::pow(eps, p - 2.0);
+    constexpr bool GE = rhvp_gram_in_edge<T, K>();
+    if (GE && g->gram_part == nullptr) {
+        set_error("rhvp: the graph handle holds no Gram area (k_max = %d)", g->k_max);
+        return PSPEC_ERR_ARG;
+    }
     const pspec_status st =
-        MODE == HESS ? edge_pass<T, WT, K, HESS>(g, k, U, ldu, V, ldv, nullptr, 0, RH, ldrh, p, eps, F_col, nullptr, s,
-                                                 true, RG, ldrg)
-                     : edge_pass<T, WT, K, HVP>(g, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, p, eps, F_col, nullptr, s);
+        MODE == HESS ? edge_pass<T, WT, K, HESS, false, GE>(g, k, U, ldu, V, ldv, nullptr, 0, RH, ldrh, p, eps, F_col,
+                                                            nullptr, s, true, RG, ldrg)
+                     : edge_pass<T, WT, K, HVP, false, GE>(g, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, p, eps, F_col,
+                                                           nullptr, s);
     if (st != PSPEC_OK) return st;
-    if constexpr (rhvp_fused<T, K>()) {
+    if constexpr (GE) {
+        // light tiles' partials from the edge pass, then the heavy rows', then fixed-order sums
+        const int len = kGramQ * (int)kk;
+        double *gp = g->gram_part;
+        const int64_t n_glob = g->n_chunks - g->seg_chunk_base[kSegs], nh = n_glob + g->n_split;
+        const int64_t hb = nh == 0 ? 0 : std::min<int64_t>(kGramHeavyBlocks, (nh + 63) / 64);
+        if (hb > 0)
+            gram_heavy<T, MODE><<<(unsigned)hb, kBlock, 0, s>>>(g->chunks + g->seg_chunk_base[kSegs], n_glob, g->splits,
+                                                                g->n_split, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw,
+                                                                epsc, gp + g->tiles * len);
+        double *mid1 = gp + (g->tiles + kGramHeavyBlocks) * len, *mid2 = mid1 + (int64_t)kGramMid * len;
+        double *fin = mid2 + (int64_t)(kGramMid / kTreeFan) * len;
+        const unsigned gx = (unsigned)((len + kBlock - 1) / kBlock);
+        sum_range<<<dim3(gx, kGramMid), kBlock, 0, s>>>(gp, g->tiles + hb, len, kGramMid, mid1);
+        sum_level<<<dim3(gx, kGramMid / kTreeFan), kBlock, 0, s>>>(mid1, kGramMid, len, len, mid2, nullptr);
+        sum_level<<<dim3(gx, 1), kBlock, 0, s>>>(mid2, kGramMid / kTreeFan, len, len, fin, nullptr);
+        gram_combine<MODE><<<1, kBlock, 0, s>>>(fin, k, p, g->scalars, g->k_max, Mw, Mw + kk, MG_out);
+        apply_rhvp<T, K, VEC, MODE><<<mf_grid(n), kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc,
+                                                                  p, g->scalars, g->k_max, Mw, Mw + kk);
+    } else if constexpr (rhvp_fused<T, K>()) {
         finalize_gram<T, K, MODE><<<kDenseBlocks, kBlock, 0, s>>>(n, k, U, ldu, V, ldv, RG, ldrg, RH, ldrh, pw, epsc,
                                                                   p, g->scalars, g->k_max, part);
         sum_partials(part, (int)kk, mid, Mw, MG_out, s, 2 * (int64_t)kk);

@@ -73,27 +73,91 @@ __global__ __launch_bounds__(kBlock) void k_check_col(const int32_t *__restrict_
     if (bad) atomicOr(flag, 2);
 }
 
-// Upper parts of the rows, for the objective pass: one wave per row counts the entries with a column
-// at most i (ustart[i] = rowptr[i] + that count) and checks that the row's columns do not descend;
-// any descent sets bit 4 of *flag, and the objective pass then visits every stored entry instead.
+// Upper parts of the rows, for the objective pass: per row, the count of entries with a column at
+// most i (ustart[i] = rowptr[i] + that count), and whether the row's columns do not descend; any
+// descent sets bit 4 of *flag, and the objective pass then visits every stored entry instead.  Rows
+// of at most kUpperShort entries take a group of 16 lanes each (k_upper); longer rows a whole
+// workgroup each (k_upper_long), so that a hub row does not hold one group for its whole length.
+constexpr int kUpperShort = 256;
+
 __global__ __launch_bounds__(kBlock) void k_upper(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                                 int64_t n, int64_t *__restrict__ ustart, int *__restrict__ flag) {
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    constexpr int G = 16;
+    const int gl = threadIdx.x % G;
+    const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
     int bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < n; i += waves) {
-        const int64_t beg = rowptr[i], end = rowptr[i + 1];
+    // every group of a wave takes the same number of turns, so the shuffles below see whole waves
+    const int64_t turns = (n + groups - 1) / groups;
+    for (int64_t tn = 0; tn < turns; ++tn) {
+        const int64_t i = (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G + tn * groups;
+        int64_t beg = 0, end = 0;
+        if (i < n) {
+            beg = rowptr[i];
+            end = rowptr[i + 1];
+        }
+        const bool mine = i < n && end - beg <= kUpperShort;
+        if (!mine) end = beg;
         int64_t low = 0;
-        for (int64_t q = beg + lane; q < end; q += 64) {
+        for (int64_t q = beg + gl; q < end; q += G) {
             const int32_t c = col[q];
             low += c <= (int32_t)i;
             if (q + 1 < end && col[q + 1] < c) bad = 1;
         }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
-        if (lane == 0) ustart[i] = beg + low;
+        for (int o = G / 2; o > 0; o >>= 1) low += __shfl_xor(low, o);
+        if (mine && gl == 0) ustart[i] = beg + low;
     }
-    if (__any(bad) && lane == 0) atomicOr(flag, 4);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 4);
+}
+
+__global__ __launch_bounds__(kBlock) void k_upper_long(const int64_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, int64_t n,
+                                                     int64_t *__restrict__ ustart, int *__restrict__ flag) {
+    __shared__ int32_t s_list[kBlock];
+    __shared__ int s_cnt;
+    __shared__ int64_t s_low[kBlock / 64];
+    __shared__ int s_bad[kBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+        // the long rows among base .. base + kBlock - 1 (listed in any order: each is handled once)
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        const int64_t r = base + tid;
+        if (r < n && rowptr[r + 1] - rowptr[r] > kUpperShort) s_list[atomicAdd(&s_cnt, 1)] = tid;
+        __syncthreads();
+        const int cnt = s_cnt;
+        for (int li = 0; li < cnt; ++li) {
+            const int64_t i = base + s_list[li];
+            const int64_t beg = rowptr[i], end = rowptr[i + 1];
+            int64_t low = 0;
+            int bad = 0;
+            for (int64_t q = beg + tid; q < end; q += kBlock) {
+                const int32_t c = col[q];
+                low += c <= (int32_t)i;
+                if (q + 1 < end && col[q + 1] < c) bad = 1;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
+            const bool wbad = __any(bad);
+            if (lane == 0) {
+                s_low[w] = low;
+                s_bad[w] = wbad ? 1 : 0;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int64_t tot = 0;
+                int b = 0;
+                for (int v = 0; v < kBlock / 64; ++v) {
+                    tot += s_low[v];
+                    b |= s_bad[v];
+                }
+                ustart[i] = beg + tot;
+                if (b) atomicOr(flag, 4);
+            }
+            __syncthreads();
+        }
+        __syncthreads();  // s_cnt and s_list are reused by the next range
+    }
 }
 
 // Column segment boundaries: bound[s] = the first node j with rowptr[j] >= s nnz / kSegs, so each
@@ -270,8 +334,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_emit(const int64_t *__restr
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Layout of the caller's workspace.  The first part depends on (n, k_max) only: the schedule kernels'
-// counters, the column-segment boundaries, the rows' upper starts and the FP64 partial sums of the
-// edge pass.  The schedule
+// counters, the column-segment boundaries, the rows' upper starts, the FP64 partial sums of the
+// edge pass and (k_max > 8) the Gram partials of the Riemannian call at 9 <= k <= 16.  The schedule
 // itself (chunk list, split-row list, split-row scratch) follows, sized by the counts of the graph:
 // exact once they are known, otherwise by bounds from (n, nnz) alone --
 //   heavy rows   <= min(n, nnz / (LIGHT_MAX + 1))      (each holds more than LIGHT_MAX edges)
@@ -280,7 +344,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   chunks       <= heavy rows + split chunks
 //   partial rows  = light tiles + kHeavyGridCap
 struct WsLayout {
-    size_t bcount = 0, tot = 0, bound = 0, ust = 0, part = 0, red1 = 0, sc = 0, chunks = 0, splits = 0, scr = 0;
+    size_t bcount = 0, tot = 0, bound = 0, ust = 0, part = 0, red1 = 0, sc = 0, gram = 0, chunks = 0, splits = 0,
+           scr = 0;
     size_t fixed = 0, total = 0;
 };
 
@@ -296,16 +361,17 @@ WsLayout ws_layout(int64_t n, int k_max, int64_t n_chunks, int64_t n_split, int6
         align256(sizeof(double) * (size_t)(tiles + kHeavyGridCap) * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kReduceSlices * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kScalars * (size_t)k_max),
+        pad_k(k_max) >= kGramK ? align256(sizeof(double) * (size_t)gram_area_rows(tiles) * kGramQ * kGramK * kGramK) : 0,
         align256(sizeof(Chunk) * (size_t)n_chunks),
         align256(sizeof(Split) * (size_t)n_split),
         align256(sizeof(double) * (size_t)n_split_chunks * 2 * (size_t)k_max),
     };
-    size_t *dst[] = {&L.bcount, &L.tot, &L.bound, &L.ust, &L.part, &L.red1, &L.sc, &L.chunks, &L.splits, &L.scr};
+    size_t *dst[] = {&L.bcount, &L.tot, &L.bound, &L.ust, &L.part, &L.red1, &L.sc, &L.gram, &L.chunks, &L.splits, &L.scr};
     size_t off = 0;
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < 11; ++i) {
         *dst[i] = off;
         off += parts[i];
-        if (i == 6) L.fixed = off;
+        if (i == 7) L.fixed = off;
     }
     L.total = off;
     return L;
@@ -371,8 +437,11 @@ pspec_status plan_counts(const char *who, int64_t n, int64_t nnz, const int64_t 
     // only a validated CSR is searched: the boundaries, upper starts and counts read rowptr and col
     k_seg_bounds<<<1, 64, 0, s>>>(rowptr, n, nnz, bound);
     {
-        const int64_t want = (n + kBlock / 64 - 1) / (kBlock / 64);
+        const int64_t want = (n + kBlock / 16 - 1) / (kBlock / 16);
         k_upper<<<(unsigned)(want < 65536 ? want : 65536), kBlock, 0, s>>>(
+            rowptr, col, n, reinterpret_cast<int64_t *>(mem + L.ust), flag);
+        const int64_t wl = (n + kBlock - 1) / kBlock;
+        k_upper_long<<<(unsigned)(wl < 65536 ? wl : 65536), kBlock, 0, s>>>(
             rowptr, col, n, reinterpret_cast<int64_t *>(mem + L.ust), flag);
     }
     k_plan_count<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, bound, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount);
@@ -477,6 +546,7 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->chunk_scratch = reinterpret_cast<double *>(mem + L.scr);
     g->ascending = (plan.flag & 4) == 0;
     g->ustart = reinterpret_cast<const int64_t *>(mem + L.ust);
+    g->gram_part = pad_k(k_max) >= kGramK ? reinterpret_cast<double *>(mem + L.gram) : nullptr;
     if (g->n_chunks > 0) {
         const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
         k_plan_emit<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, reinterpret_cast<const int32_t *>(mem + L.bound),

@@ -115,6 +115,23 @@ def oracle_scales(g, U, V, p, eps, sparse=False):
                           eps, sparse=sparse)
 
 
+def gram_in_edge_pass(k, dtype) -> bool:
+    """Whether pspec_rhvp / pspec_rhess form their Gram products inside the edge pass (FP32,
+    9 <= k <= 16).
+    Their MG and MH then come from U^T L, U^T J, U^T phi and U^T (psi v) combined in FP64, which
+    agrees with the Gram products of the finalized G and HV (the unfused sequence) to rounding, not
+    bit for bit."""
+    return 9 <= k <= 16 and dtype == torch.float32
+
+
+def riemannian_scales(U, V, SG, SH):
+    """Element-wise scales of RG = G - U (U^T G), RH = HV - U (U^T HV) - V (U^T G) and MG = U^T G:
+    the forward-error scales of G and HV carried through the products (U, V as FP64 arrays)."""
+    aU, aV = np.abs(U), np.abs(V)
+    MGs = aU.T @ SG
+    return SG + aU @ MGs, SH + aU @ (aU.T @ SH) + aV @ MGs, MGs
+
+
 def errors(HVg, Gg, Fcg, HVo, Go, Fco, SG, SH) -> dict:
     """Every error measure of one grad+HVP result against the oracle's."""
     return dict(

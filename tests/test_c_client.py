@@ -31,6 +31,6 @@ def test_c_client_links_and_runs(tmp_path):
     assert "graph_create small workspace -> 4" in out
     assert "graph workspace k=65: 0 bytes" in out
     gws = int(out.split("graph workspace n=8000000 nnz=95998824 k=16: ")[1].split()[0])
-    assert 400e6 < gws < 700e6  # the bound from (n, nnz, k_max) alone; an exact size is usually far smaller
+    assert 400e6 < gws < 1e9  # the bound from (n, nnz, k_max) alone; an exact size is usually far smaller
     ws = int(out.split("dense workspace k=16: ")[1].split()[0])
     assert ws >= 2 * 1024 * 16 * 16 * 8

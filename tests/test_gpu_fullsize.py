@@ -36,7 +36,8 @@ def test_fullsize_vs_oracle(name):
         print(f"{name} {dtype}:", end=" ")
         gu.check(e, dtype)
         del HV, G
-    # the fused Riemannian call equals the unfused sequence bit for bit at full size
+    # the fused Riemannian call against the unfused sequence at full size: bit for bit, or within
+    # 2 tau entry by entry where the Gram products are formed in the edge pass
     P = torch.empty((g.n, 2 * k), dtype=torch.float32, device="cuda")
     P[:, :k] = torch.as_tensor(U)
     P[:, k:] = torch.as_tensor(V)
@@ -45,18 +46,27 @@ def test_fullsize_vs_oracle(name):
     HV, G, _ = pspec.hvp(dg, Ut, Vt, p, eps)
     RG2, MG2 = pspec.project(Ut, G)
     RH2, _ = pspec.project(Ut, HV, X=Vt, MX=MG2)
-    assert torch.equal(RG, RG2) and torch.equal(MG, MG2) and torch.equal(RH, RH2)
-    # the fixed-U call of the truncated-CG loop: same MG and F_col, RH within the element-wise bound
+    Uh, Vh = Ut.double().cpu().numpy(), Vt.double().cpu().numpy()
+    S_RG, S_RH, S_MG = gu.riemannian_scales(Uh, Vh, SG, SH)
+    tau = gu.TOLS[torch.float32]["tau"]
+    if gu.gram_in_edge_pass(k, torch.float32):
+        for nm, a, b, S in (("RG", RG, RG2, S_RG), ("RH", RH, RH2, S_RH), ("MG", MG, MG2, S_MG)):
+            d = gu.ew(a.double().cpu().numpy(), b.double().cpu().numpy(), S)
+            print(f"{name}: rhvp vs unfused {nm} element-wise {d:.2e}", flush=True)
+            assert d <= 2 * tau, nm
+    else:
+        assert torch.equal(RG, RG2) and torch.equal(MG, MG2) and torch.equal(RH, RH2)
+    # the fixed-U call of the truncated-CG loop: same F_col, MG and RH within the element-wise bound
     # of rhvp's (the scale of G and HV carried through the two Gram products)
     RH3, MG3, _ = pspec.rhess(dg, Ut, Vt, G, p, eps)
     torch.cuda.synchronize()
-    assert torch.equal(MG, MG3)
-    Uh, Vh = Ut.double().cpu().numpy(), Vt.double().cpu().numpy()
-    aU, aV = np.abs(Uh), np.abs(Vh)
-    S_RH = SH + aU @ (aU.T @ SH) + aV @ (aU.T @ SG)
+    if gu.gram_in_edge_pass(k, torch.float32):
+        assert gu.ew(MG3.cpu().numpy(), MG.cpu().numpy(), S_MG) <= 2 * tau
+    else:
+        assert torch.equal(MG, MG3)
     d = gu.ew(RH3.double().cpu().numpy(), RH.double().cpu().numpy(), S_RH)
     print(f"{name}: rhess vs rhvp element-wise {d:.2e}", flush=True)
-    assert d <= 2 * gu.TOLS[torch.float32]["tau"]
+    assert d <= 2 * tau
     del P, RH, RG, HV, G, RG2, RH2, RH3
     if name == "rmat22":
         assert info["heavy_rows"] > 0 and info["split_rows"] > 0
