@@ -57,6 +57,26 @@ struct PowM2<float> {
         return __builtin_amdgcn_exp2f(pm2 * __builtin_amdgcn_logf(ax));
     }
 };
+// FP64 fused multiply-add whose addend (vvs) or multiplier (vsv) is wave-uniform, taken from an SGPR
+// pair: one v_fma_f64.  Left to itself the compiler keeps the series coefficients below in VGPRs and
+// copies one into the destination before every step (v_mov_b64 + v_fmac_f64), which doubles the
+// instruction count of the FP64 power.  Same operation, same rounding as fma().
+__device__ __forceinline__ double fma_vvs(double a, double b, double c) {
+    double r;
+    __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+__device__ __forceinline__ double fma_vsv(double a, double b, double c) {
+    double r;
+    __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ double fma_neg_vsv(double a, double b, double c) {  // -a b + c
+    double r;
+    __asm__("v_fma_f64 %0, -%1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 template <>
 struct PowM2<double> {
     double pm2;
@@ -74,17 +94,16 @@ struct PowM2<double> {
         const double f = m - 1.0;  // exact
         const double sv = f / (f + 2.0);
         const double R = sv * sv;
-        double P = 1.0 / 23.0;
-        P = fma(P, R, 1.0 / 21.0);
-        P = fma(P, R, 1.0 / 19.0);
-        P = fma(P, R, 1.0 / 17.0);
-        P = fma(P, R, 1.0 / 15.0);
-        P = fma(P, R, 1.0 / 13.0);
-        P = fma(P, R, 1.0 / 11.0);
-        P = fma(P, R, 1.0 / 9.0);
-        P = fma(P, R, 1.0 / 7.0);
-        P = fma(P, R, 1.0 / 5.0);
-        P = fma(P, R, 1.0 / 3.0);
+        double P = fma_vsv(R, 1.0 / 23.0, 1.0 / 21.0);
+        P = fma_vvs(P, R, 1.0 / 19.0);
+        P = fma_vvs(P, R, 1.0 / 17.0);
+        P = fma_vvs(P, R, 1.0 / 15.0);
+        P = fma_vvs(P, R, 1.0 / 13.0);
+        P = fma_vvs(P, R, 1.0 / 11.0);
+        P = fma_vvs(P, R, 1.0 / 9.0);
+        P = fma_vvs(P, R, 1.0 / 7.0);
+        P = fma_vvs(P, R, 1.0 / 5.0);
+        P = fma_vvs(P, R, 1.0 / 3.0);
         const double lnm = fma(2.0 * sv, R * P, 2.0 * sv);  // 2 s (1 + R P)
         const double de = (double)e;
         const double a = de * kLn2Hi;                        // exact; |a| > |ln m| unless e = 0
@@ -93,19 +112,18 @@ struct PowM2<double> {
         const double th = pm2 * hi;
         const double tl = fma(pm2, hi, -th) + pm2 * lo;
         const double n = rint(th * kLog2e);
-        double r = fma(-n, kLn2Hi, th);
-        r = fma(-n, kLn2Lo, r) + tl;
-        double E = 1.0 / 6227020800.0;  // 1/13!
-        E = fma(E, r, 1.0 / 479001600.0);
-        E = fma(E, r, 1.0 / 39916800.0);
-        E = fma(E, r, 1.0 / 3628800.0);
-        E = fma(E, r, 1.0 / 362880.0);
-        E = fma(E, r, 1.0 / 40320.0);
-        E = fma(E, r, 1.0 / 5040.0);
-        E = fma(E, r, 1.0 / 720.0);
-        E = fma(E, r, 1.0 / 120.0);
-        E = fma(E, r, 1.0 / 24.0);
-        E = fma(E, r, 1.0 / 6.0);
+        double r = fma_neg_vsv(n, kLn2Hi, th);
+        r = fma_neg_vsv(n, kLn2Lo, r) + tl;
+        double E = fma_vsv(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);  // 1/13!, 1/12!
+        E = fma_vvs(E, r, 1.0 / 39916800.0);
+        E = fma_vvs(E, r, 1.0 / 3628800.0);
+        E = fma_vvs(E, r, 1.0 / 362880.0);
+        E = fma_vvs(E, r, 1.0 / 40320.0);
+        E = fma_vvs(E, r, 1.0 / 5040.0);
+        E = fma_vvs(E, r, 1.0 / 720.0);
+        E = fma_vvs(E, r, 1.0 / 120.0);
+        E = fma_vvs(E, r, 1.0 / 24.0);
+        E = fma_vvs(E, r, 1.0 / 6.0);
         E = fma(E, r, 0.5);
         E = fma(E, r, 1.0);
         E = fma(E, r, 1.0);
