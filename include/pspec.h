@@ -35,11 +35,11 @@
  * Types.   dt = PSPEC_F32: U/V/G/HV are float; edge arithmetic in FP32 (|x|^(p-2) as
  *          exp2((p-2) log2 max(|x|, 2^-64)) with the hardware exp2/log2), every reduction (numerators,
  *          p-norms, dot products, Gram matrices) in FP64.
- *          dt = PSPEC_F64: everything double; |x|^(p-2) by the library's own exp((p-2) ln x) (ln x
- *          from an atanh series in double-double, exp by a Taylor series after reduction by ln 2;
- *          within a few units in the last place of the C library's pow), with x clamped to
- *          [2^-512, inf) (so only 0 < |x| < 2^-512 is affected; exact zeros stay exact) and exactly 1
- *          at p = 2.
+ *          dt = PSPEC_F64: everything double; |x|^(p-2) by the library's own exp((p-2) ln x),
+ *          table-driven (Tang's logarithm and exponential: 128-entry tables, ln x and (p-2) ln x
+ *          in double-double; within 0.52 units in the last place of the C library's pow on a CPU
+ *          transcription), with x clamped to [2^-512, inf) (so only 0 < |x| < 2^-512 is affected;
+ *          exact zeros stay exact) and exactly 1 at p = 2.
  * Errors.  Argument errors are found on the host before anything is launched and return
  *          PSPEC_ERR_ARG (PSPEC_ERR_UNSUPPORTED for valid but unsupported requests); a failed HIP
  *          call returns PSPEC_ERR_HIP.  pspec_last_error() describes the last failure of the

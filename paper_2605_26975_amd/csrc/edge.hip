@@ -39,14 +39,19 @@ constexpr bool mode_v(int m) { return m == HVP || m == HESS; }  // reads V, form
 
 // |x|^(p-2) for x >= 0.  FP32: hardware exp2/log2 on max(x, 2^-64), so an exact zero gives a finite
 // value (2^(64 (2-p))) whose product with x is exactly 0.  FP64: exp(q ln x) for x clamped to
-// [2^-512, inf), q = p - 2, written out for this one use (the general pow() handles cases that
-// cannot occur here and costs several times as many instructions, which bounds the FP64 edge pass):
-//   x = 2^e m, m in [1/sqrt 2, sqrt 2);  ln m = 2 atanh(s), s = (m - 1)/(m + 1), by the odd series
-//   sum s^(2j+1)/(2j+1) to j = 11 (|s| <= 0.172: truncation below 2^-60);  ln x = e ln 2 + ln m and
-//   t = q ln x as double-doubles (ln 2 split so that e ln2_hi is exact);  exp(t) = 2^n exp(r),
-//   n = rint(t / ln 2), |r| <= ln 2 / 2, exp(r) by its Taylor series to r^13 (truncation below
-//   2^-57).  A few units in the last place; q = 0 gives exactly 1 (and is returned at once: p = 2 is
-//   the first level of every continuation); x = inf gives pow()'s limits.
+// [2^-512, inf), q = p - 2, table-driven after Tang (ACM TOMS 1989 and 1990), written out for this one
+// use (the general pow() handles cases that cannot occur here and costs several times as many
+// instructions, which bounds the FP64 edge pass):
+//   x = 2^e m, m in [1, 2); j = the top 7 bits of m's fraction; r = m C_j - 1 (|r| <= 2^-8, one FMA),
+//   C_j ~ 1 / (1 + (j + 1/2) / 128);  ln x = e ln 2 + (-ln C_j) + ln(1 + r), the series of ln(1 + r) to
+//   r^8 (truncation below 2^-67), -ln C_j a double-double from the table, e ln 2 with ln 2 split so
+//   that e ln2_hi is exact;  t = q ln x as a double-double;
+//   exp(t) = 2^(n / 128) exp(s), n = rint(128 t / ln 2), |s| <= ln 2 / 256, exp(s) by its Taylor series
+//   to s^6 (truncation below 2^-72), 2^(k / 128) (k = n mod 128) a double-double from the table.
+// A transcription on the CPU is within 0.52 units in the last place of pow over x in [1e-150, 1e3],
+// q in [-0.95, 0.5].  q = 0 gives exactly 1 (and is returned at once: p = 2 is the first level of every
+// continuation); x = inf gives pow()'s limits.  The tables (pow_tables.inc, from gen_pow_tables.py) are
+// staged into LDS by every kernel that evaluates the FP64 power (stage_pow).
 template <typename T>
 struct PowM2;
 template <>
@@ -57,10 +62,16 @@ struct PowM2<float> {
         return __builtin_amdgcn_exp2f(pm2 * __builtin_amdgcn_logf(ax));
     }
 };
+
+constexpr int kPowTabLen = 5 * 128;  // C, LH, LL (logarithm), TH, TL (exponential)
+__device__ const double kPowTab[kPowTabLen] = {
+#include "pow_tables.inc"
+};
+
 // FP64 fused multiply-add whose addend (vvs) or multiplier (vsv) is wave-uniform, taken from an SGPR
-// pair: one v_fma_f64.  Left to itself the compiler keeps the series coefficients below in VGPRs and
-// copies one into the destination before every step (v_mov_b64 + v_fmac_f64), which doubles the
-// instruction count of the FP64 power.  Same operation, same rounding as fma().
+// pair: one v_fma_f64.  Left to itself the compiler keeps series coefficients in VGPRs and copies one
+// into the destination before every step (v_mov_b64 + v_fmac_f64), which doubles the instruction
+// count of the FP64 power.  Same operation, same rounding as fma().
 __device__ __forceinline__ double fma_vvs(double a, double b, double c) {
     double r;
     __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
@@ -80,58 +91,59 @@ __device__ __forceinline__ double fma_neg_vsv(double a, double b, double c) {  /
 template <>
 struct PowM2<double> {
     double pm2;
+    const double *tab = nullptr;  // the kernel's LDS copy of kPowTab (set by stage_pow)
     __device__ __forceinline__ double operator()(double ax) const {
         constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;  // ln 2 to 42 bits: e * kLn2Hi is exact
         constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
-        constexpr double kLog2e = 0x1.71547652b82fep0;
+        constexpr double k128Log2e = 0x1.71547652b82fep0 * 128.0;
         if (pm2 == 0.0) return 1.0;  // p = 2 (uniform branch): the routine below gives exactly 1 too
         const double x = fmax(ax, 0x1p-512);
         int e;
-        double m = frexp(x, &e);  // [1/2, 1)
-        const bool low = m < 0x1.6a09e667f3bcdp-1;
-        m = low ? 2.0 * m : m;
-        e = low ? e - 1 : e;
-        const double f = m - 1.0;  // exact
-        const double sv = f / (f + 2.0);
-        const double R = sv * sv;
-        double P = fma_vsv(R, 1.0 / 23.0, 1.0 / 21.0);
-        P = fma_vvs(P, R, 1.0 / 19.0);
-        P = fma_vvs(P, R, 1.0 / 17.0);
-        P = fma_vvs(P, R, 1.0 / 15.0);
-        P = fma_vvs(P, R, 1.0 / 13.0);
-        P = fma_vvs(P, R, 1.0 / 11.0);
-        P = fma_vvs(P, R, 1.0 / 9.0);
-        P = fma_vvs(P, R, 1.0 / 7.0);
-        P = fma_vvs(P, R, 1.0 / 5.0);
-        P = fma_vvs(P, R, 1.0 / 3.0);
-        const double lnm = fma(2.0 * sv, R * P, 2.0 * sv);  // 2 s (1 + R P)
-        const double de = (double)e;
-        const double a = de * kLn2Hi;                        // exact; |a| > |ln m| unless e = 0
-        const double hi = a + lnm;
-        const double lo = ((a - hi) + lnm) + de * kLn2Lo;
+        const double m = frexp(x, &e);  // [1/2, 1): the same fraction bits as 2m in [1, 2)
+        const int j = (int)((uint32_t)__double2hiint(m) >> 13) & 127;
+        const double C = tab[j], LH = tab[128 + j], LL = tab[256 + j];
+        const double r = fma(m + m, C, -1.0);  // exact scaling of m, one rounding
+        const double r2 = r * r;
+        double P = fma_vsv(r, -1.0 / 8.0, 1.0 / 7.0);
+        P = fma_vvs(P, r, -1.0 / 6.0);
+        P = fma_vvs(P, r, 1.0 / 5.0);
+        P = fma_vvs(P, r, -1.0 / 4.0);
+        P = fma_vvs(P, r, 1.0 / 3.0);
+        P = fma(P, r, -0.5);
+        const double lp = fma(r2, P, r);  // ln(1 + r)
+        const double de = (double)(e - 1);
+        const double a = de * kLn2Hi;  // exact; |a| >= ln 2 >= |LH| unless e = 1
+        const double hi = a + LH;
+        const double lo = ((a - hi) + LH) + (fma_vsv(de, kLn2Lo, LL) + lp);
         const double th = pm2 * hi;
         const double tl = fma(pm2, hi, -th) + pm2 * lo;
-        const double n = rint(th * kLog2e);
-        double r = fma_neg_vsv(n, kLn2Hi, th);
-        r = fma_neg_vsv(n, kLn2Lo, r) + tl;
-        double E = fma_vsv(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);  // 1/13!, 1/12!
-        E = fma_vvs(E, r, 1.0 / 39916800.0);
-        E = fma_vvs(E, r, 1.0 / 3628800.0);
-        E = fma_vvs(E, r, 1.0 / 362880.0);
-        E = fma_vvs(E, r, 1.0 / 40320.0);
-        E = fma_vvs(E, r, 1.0 / 5040.0);
-        E = fma_vvs(E, r, 1.0 / 720.0);
-        E = fma_vvs(E, r, 1.0 / 120.0);
-        E = fma_vvs(E, r, 1.0 / 24.0);
-        E = fma_vvs(E, r, 1.0 / 6.0);
-        E = fma(E, r, 0.5);
-        E = fma(E, r, 1.0);
-        E = fma(E, r, 1.0);
-        const double y = ldexp(E, (int)n);
+        const double n = rint(th * k128Log2e);
+        double s = fma_neg_vsv(n, kLn2Hi / 128.0, th);
+        s = fma_neg_vsv(n, kLn2Lo / 128.0, s) + tl;
+        double E = fma_vsv(s, 1.0 / 720.0, 1.0 / 120.0);
+        E = fma_vvs(E, s, 1.0 / 24.0);
+        E = fma_vvs(E, s, 1.0 / 6.0);
+        E = fma(E, s, 0.5);
+        E = fma(E * s, s, s);  // exp(s) - 1
+        const int ni = (int)n;
+        const int k = ni & 127;
+        const double TH = tab[384 + k], TL = tab[512 + k];
+        const double y = ldexp(fma(TH, E, fma(TL, E, TL)) + TH, ni >> 7);  // 2^(n/128) (1 + E)
         // x = inf (a non-finite U): the limits of pow (0, 1 or inf by the sign of q); NaN stays NaN
         return x < __builtin_inf() ? y : (pm2 < 0.0 ? 0.0 : (pm2 == 0.0 ? 1.0 : x));
     }
 };
+
+// Stage the FP64 power's tables into the kernel's LDS array s (kPowTabLen doubles) and point pw at
+// it; a no-op for FP32.  Every thread of the workgroup must call it before its first power.
+template <typename T>
+__device__ __forceinline__ void stage_pow(PowM2<T> &pw, double *s) {
+    if constexpr (sizeof(T) == 8) {
+        for (int i = threadIdx.x; i < kPowTabLen; i += blockDim.x) s[i] = kPowTab[i];
+        __syncthreads();
+        pw.tab = s;
+    }
+}
 
 template <typename T, typename WT>
 struct EdgeArgs {
@@ -273,7 +285,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     __shared__ int64_t s_up[MODE == OBJ ? kTileRows : 1];
     __shared__ double s_red[kBlock / 64][kQ][K];
     __shared__ double s_gred[GRAM ? kBlock / 64 : 1][4][64];
+    __shared__ double s_pow[sizeof(T) == 8 ? kPowTabLen : 1];
     static_assert(!GRAM || (K == 16 && (MODE == HVP || MODE == HESS) && !FLOOR), "Gram products: k = 16, HVP or HESS");
+    PowM2<T> pw = a.pw;  // a local copy (taking the address of the argument block would move it to scratch)
+    stage_pow(pw, s_pow);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -400,7 +415,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                     const T wv = edge_bcast_val<T, G, EPR, u>(wl, e, lane);
 #pragma unroll
                     for (int m = 0; m < CPL; ++m)
-                        Term<T, MODE, FLOOR>::apply(a.pw, a.epsc, cur.ui[m], uj[u][m], cur.vi[m], vj[u][m], wv, Ls[m],
+                        Term<T, MODE, FLOOR>::apply(pw, a.epsc, cur.ui[m], uj[u][m], cur.vi[m], vj[u][m], wv, Ls[m],
                                              Js[m], Ns[m]);
                 }
             });
@@ -419,7 +434,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
             }
             q[0][m] += (double)Ns[m];
             const T ui = cur.ui[m], vi = cur.vi[m];
-            const T hi = a.pw(fabs(ui));
+            const T hi = pw(fabs(ui));
             const T phi = hi * ui;  // phi_p(u_i)
             // HESS: g_i read here (not held through the row); own is row 0 past the last row
             const T gi = MODE == HESS ? bload<T>(rG, own * a.ldg_b + cb[m]) : T(0);
@@ -491,6 +506,9 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
     __shared__ uint32_t s_ou[NWB][PSPEC_CHUNK], s_ov[NWB][PSPEC_CHUNK];  // neighbour byte offsets into U, V
     __shared__ T s_w[NWB][PSPEC_CHUNK];
     __shared__ double s_acc[NWB][2][KW];
+    __shared__ double s_pow[sizeof(T) == 8 ? kPowTabLen : 1];
+    PowM2<T> pw = a.pw;  // a local copy (taking the address of the argument block would move it to scratch)
+    stage_pow(pw, s_pow);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int c = lane % KW, e = lane / KW;
     const int cl = c < a.k ? c : a.k - 1;
@@ -570,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
             }
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
-                Term<T, MODE, FLOOR>::apply(a.pw, a.epsc, ui, uj[u], vi, vj[u], wt[u], Ls, Js, Ns);
+                Term<T, MODE, FLOOR>::apply(pw, a.epsc, ui, uj[u], vi, vj[u], wt[u], Ls, Js, Ns);
         }
         double L = (double)Ls, J = (double)Js, N = (double)Ns;
 #pragma unroll
@@ -737,6 +755,8 @@ __global__ __launch_bounds__(kBlock) void finalize(int64_t n, int k, const T *__
                                                  const T *__restrict__ V, int64_t ldv, T *__restrict__ G, int64_t ldg,
                                                  T *__restrict__ HV, int64_t ldh, PowM2<T> pw, T epsc, double p,
                                                  const double *__restrict__ sc, int k_max) {
+    __shared__ double s_pow[sizeof(T) == 8 ? kPowTabLen : 1];
+    stage_pow(pw, s_pow);
     const int64_t stride = (int64_t)gridDim.x * (kBlock / K);
     const int c = threadIdx.x % K;
     if (c >= k) return;
@@ -765,6 +785,8 @@ __global__ __launch_bounds__(kBlock) void finalize_gram(int64_t n, int k, const 
                                                       double *__restrict__ part) {
     constexpr int CT = mf_tiles<K>();
     __shared__ double s_red[4][4][64];
+    __shared__ double s_pow[sizeof(T) == 8 ? kPowTabLen : 1];
+    stage_pow(pw, s_pow);
     const int c = threadIdx.x & 15;
     ColScalars cs[CT];  // this lane's columns 16 t + c
 #pragma unroll
@@ -826,6 +848,8 @@ __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *
                                                    double p, const double *__restrict__ sc, int k_max,
                                                    const double *__restrict__ MG, const double *__restrict__ MH) {
     constexpr int CT = mf_tiles<K>(), KS = mf_steps<K>();
+    __shared__ double s_pow[sizeof(T) == 8 ? kPowTabLen : 1];
+    stage_pow(pw, s_pow);
     const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
     double mg[CT][KS], mh[CT][KS];
     load_mf_operand<K>(MG, k, mg);
@@ -908,11 +932,13 @@ __global__ __launch_bounds__(kBlock) void apply_rhvp(int64_t n, int k, const T *
 }
 
 // Gathers in flight per lane in the heavy-chunk kernel: 32 edges per wave (64 / K edge slots), at
-// most 8 per lane (more registers per wave cost more in resident waves than they gain).
+// most 8 per lane (more registers per wave cost more in resident waves than they gain); at most 4 in
+// FP64, whose pass is bound by the arithmetic of the power, not by the gathers.
 template <typename T, int K>
 constexpr int heavy_unroll() {
     constexpr int slots = K < 64 ? 64 / K : 1;
-    return 32 / slots > 8 ? 8 : (32 / slots < 2 ? 2 : 32 / slots);
+    constexpr int cap = sizeof(T) == 8 ? 4 : 8;
+    return 32 / slots > cap ? cap : (32 / slots < 2 ? 2 : 32 / slots);
 }
 
 // Workgroups of the persistent heavy-chunk kernel for this element type and k: as many as stay
@@ -1034,6 +1060,8 @@ __global__ __launch_bounds__(kBlock) void gram_heavy(const Chunk *__restrict__ g
                                                    const T *__restrict__ J, int64_t ldj, PowM2<T> pw, T epsc,
                                                    double *__restrict__ part) {
     __shared__ double s_red[4][4][64];
+    __shared__ double s_pow[sizeof(T) == 8 ? kPowTabLen : 1];
+    stage_pow(pw, s_pow);
     int64_t r0, r1;
     block_rows(n_glob + n_split, r0, r1);
     auto row_of = [&](int64_t h) -> int64_t { return h < n_glob ? (int64_t)glob[h].row : (int64_t)splits[h - n_glob].row; };
