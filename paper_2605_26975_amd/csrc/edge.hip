@@ -265,6 +265,14 @@ constexpr int light_cpl() {
     return K > 16 ? K / 16 : 1;
 }
 
+// Batches in which the light kernel issues and consumes the gathers of one chunk of G edges: all at
+// once in FP32, whose pass is bound by the gathers; in 2 (k <= 16) or 4 batches in FP64, whose pass
+// is bound by the arithmetic of the power and gains resident waves from the registers this frees.
+template <typename T, int K>
+constexpr int light_batches() {
+    return sizeof(T) == 8 ? (K >= 32 ? 4 : 2) : 1;
+}
+
 // Waves per SIMD the light kernel is compiled for (k = 32 in FP32 sits just above 128 VGPRs).
 template <typename T, int K, bool GRAM = false>
 constexpr int light_waves() {
@@ -390,34 +398,40 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                     wl2 = (T)a.w[c1 + gl];
                 }
             }
-            T uj[NU][CPL], vj[NU][CPL];
-            static_for<0, NU>([&](auto uc) {
-                constexpr int u = decltype(uc)::value;
-#pragma unroll
-                for (int m = 0; m < CPL; ++m) {
-                    uj[u][m] = cur.ui[m];
-                    vj[u][m] = cur.vi[m];
-                }
-                if (u * EPR < cnt) {
-                    const uint32_t bu = (uint32_t)edge_bcast<G, EPR, u>((int32_t)ou, e, lane);
-                    const uint32_t bv = mode_v(MODE) ? (uint32_t)edge_bcast<G, EPR, u>((int32_t)ov, e, lane) : 0u;
+            constexpr int NBAT = light_batches<T, K>();
+            constexpr int BU = NU / NBAT;
+            static_for<0, NBAT>([&](auto bc) {
+                constexpr int b0 = decltype(bc)::value * BU;
+                T uj[BU][CPL], vj[BU][CPL];
+                static_for<0, BU>([&](auto uc) {
+                    constexpr int r = decltype(uc)::value;
+                    constexpr int u = b0 + r;
 #pragma unroll
                     for (int m = 0; m < CPL; ++m) {
-                        uj[u][m] = bload<T>(rU, bu + cb[m]);
-                        if (mode_v(MODE)) vj[u][m] = bload<T>(rV, bv + cb[m]);
+                        uj[r][m] = cur.ui[m];
+                        vj[r][m] = cur.vi[m];
                     }
-                }
-            });
-            // every gather of the chunk is in flight before the first one is used
-            static_for<0, NU>([&](auto uc) {
-                constexpr int u = decltype(uc)::value;
-                if (u * EPR < cnt) {
-                    const T wv = edge_bcast_val<T, G, EPR, u>(wl, e, lane);
+                    if (u * EPR < cnt) {
+                        const uint32_t bu = (uint32_t)edge_bcast<G, EPR, u>((int32_t)ou, e, lane);
+                        const uint32_t bv = mode_v(MODE) ? (uint32_t)edge_bcast<G, EPR, u>((int32_t)ov, e, lane) : 0u;
 #pragma unroll
-                    for (int m = 0; m < CPL; ++m)
-                        Term<T, MODE, FLOOR>::apply(pw, a.epsc, cur.ui[m], uj[u][m], cur.vi[m], vj[u][m], wv, Ls[m],
-                                             Js[m], Ns[m]);
-                }
+                        for (int m = 0; m < CPL; ++m) {
+                            uj[r][m] = bload<T>(rU, bu + cb[m]);
+                            if (mode_v(MODE)) vj[r][m] = bload<T>(rV, bv + cb[m]);
+                        }
+                    }
+                });
+                static_for<0, BU>([&](auto uc) {
+                    constexpr int r = decltype(uc)::value;
+                    constexpr int u = b0 + r;
+                    if (u * EPR < cnt) {
+                        const T wv = edge_bcast_val<T, G, EPR, u>(wl, e, lane);
+#pragma unroll
+                        for (int m = 0; m < CPL; ++m)
+                            Term<T, MODE, FLOOR>::apply(pw, a.epsc, cur.ui[m], uj[r][m], cur.vi[m], vj[r][m], wv,
+                                                        Ls[m], Js[m], Ns[m]);
+                    }
+                });
             });
             ou = ou2;
             ov = ov2;
