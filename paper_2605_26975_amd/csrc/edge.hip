@@ -173,6 +173,7 @@ struct EdgeArgs {
     const int64_t *ustart;        // OBJ over rows with ascending columns: the first entry j > i of each
                                   // row (each undirected edge visited once); otherwise NULL
     double *gpart;                // light kernel with Gram products: [tiles][kGramQ][k][k]
+    const int32_t *lperm;         // light tiles' rows in degree order, or NULL (node order)
 };
 
 // One edge-column term.  wv is the weight (0 for padding lanes, whose gather is the row itself).
@@ -289,7 +290,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     constexpr int NGRP = kBlock / G;
     constexpr int RS = kTileRows / NGRP;
     static_assert(kTileRows % NGRP == 0, "tile rows must split evenly over groups");
-    __shared__ int64_t s_rp[kTileRows + 1];
+    __shared__ int64_t s_b[kTileRows], s_e[kTileRows];  // each slot's row: first and past-the-last entry
+    __shared__ int32_t s_row[kTileRows];
     __shared__ int64_t s_up[MODE == OBJ ? kTileRows : 1];
     __shared__ double s_red[kBlock / 64][kQ][K];
     __shared__ double s_gred[GRAM ? kBlock / 64 : 1][4][64];
@@ -308,19 +310,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
         const int cm = c + m * KL;
         cb[m] = (uint32_t)(cm < a.k ? cm : a.k - 1) * (uint32_t)sizeof(T);
     }
+    // slot t of the tile takes row row0 + t, or the tile's t-th row in degree order (lperm); slots past
+    // the last row are empty
     const int64_t row0 = (int64_t)blockIdx.x * kTileRows;
-    for (int t = tid; t <= kTileRows; t += kBlock) {
-        const int64_t r = row0 + t;
-        s_rp[t] = a.rowptr[r < a.n ? r : a.n];
-        if (MODE == OBJ && a.ustart != nullptr && t < kTileRows && r < a.n) s_up[t] = a.ustart[r];
+    for (int t = tid; t < kTileRows; t += kBlock) {
+        const int64_t slot = row0 + t;
+        const int64_t r = slot < a.n ? (a.lperm != nullptr ? (int64_t)a.lperm[slot] : slot) : a.n;
+        s_row[t] = (int32_t)(slot < a.n ? r : 0);
+        s_b[t] = a.rowptr[r];
+        s_e[t] = slot < a.n ? a.rowptr[r + 1] : s_b[t];
+        if (MODE == OBJ && a.ustart != nullptr && slot < a.n) s_up[t] = a.ustart[r];
     }
     __syncthreads();
-    // first entry of row rl this pass visits: the whole row, or its entries j > i (OBJ, ascending)
+    // first entry of slot rl's row this pass visits: the whole row, or its entries j > i (OBJ, ascending)
     auto first = [&](int rl) -> int64_t {
         if constexpr (MODE == OBJ) {
             if (a.ustart != nullptr) return s_up[rl];
         }
-        return s_rp[rl];
+        return s_b[rl];
     };
 
     const auto rU = make_rsrc(a.U, a.U_bytes);
@@ -335,8 +342,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     };
     auto prefetch = [&](int rl) {
         RowPre r;
-        const int64_t row = row0 + rl;
-        const bool valid = row < a.n;
+        const bool valid = row0 + rl < a.n;
+        const int64_t row = s_row[rl];
         uint32_t j = valid ? (uint32_t)row : 0u;
 #pragma unroll
         for (int m = 0; m < CPL; ++m) {
@@ -345,8 +352,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
         }
         r.wl = (T)0;
         if (valid) {
-            const int64_t b = first(rl), d = s_rp[rl + 1] - s_rp[rl];
-            if (d <= a.light_max && gl < s_rp[rl + 1] - b) {
+            const int64_t b = first(rl), d = s_e[rl] - s_b[rl];
+            if (d <= a.light_max && gl < s_e[rl] - b) {
                 j = (uint32_t)a.col[b + gl];
                 r.wl = (T)a.w[b + gl];
             }
@@ -369,10 +376,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
     for (int i = 0; i < (GRAM ? kGramQ : 1); ++i) gacc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < RS; ++s) {
         const int rl = grp + s * NGRP;
-        const int64_t row = row0 + rl;
-        const bool valid = row < a.n;
-        const int64_t beg = valid ? first(rl) : 0, end = valid ? s_rp[rl + 1] : 0;
-        const bool light = valid && (end - s_rp[rl]) <= a.light_max;
+        const bool valid = row0 + rl < a.n;
+        const int64_t row = s_row[rl];
+        const int64_t beg = valid ? first(rl) : 0, end = valid ? s_e[rl] : 0;
+        const bool light = valid && (end - s_b[rl]) <= a.light_max;
         const int64_t len = light ? end - beg : 0;
         const uint32_t own = valid ? (uint32_t)row : 0u;
         const RowPre cur = nxt;
@@ -1021,6 +1028,7 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.n_chunks = g->n_chunks;
     a.ustart = (MODE == OBJ && g->ascending) ? g->ustart : nullptr;
     a.gpart = GRAM ? g->gram_part : nullptr;
+    a.lperm = g->lperm;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
     edge_light<T, WT, K, MODE, FLOOR, GRAM><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     const int64_t hb = heavy_grid<T, WT, K>(g);

@@ -46,10 +46,12 @@ namespace {
 
 constexpr int kPlanBlock = 256;  // rows per block of the schedule kernels
 // Per-row counters of the schedule: heavy rows, chunks of the shared list (rows of LIGHT_MAX + 1 ..
-// CHUNK edges, one chunk each), split rows (more than CHUNK edges), their chunks, and their chunks in
-// each of the kSegs column segments.
+// CHUNK edges, one chunk each), split rows (more than CHUNK edges), their chunks, their chunks in
+// each of the kSegs column segments, and the count, degree sum and squared-degree sum of the light
+// rows (whether to order each tile's rows by degree).
 constexpr int kCHeavy = 0, kCGlob = 1, kCSplit = 2, kCSplitChunks = 3, kCSeg = 4;
-constexpr int kCounters = kCSeg + kSegs;
+constexpr int kCLight = kCSeg + kSegs, kCDeg = kCLight + 1, kCDeg2 = kCLight + 2;
+constexpr int kCounters = kCDeg2 + 1;
 
 __global__ __launch_bounds__(kBlock) void k_check_rowptr(const int64_t *__restrict__ rowptr, int64_t n, int64_t nnz,
                                                        int *__restrict__ flag) {
@@ -160,6 +162,30 @@ __global__ __launch_bounds__(kBlock) void k_upper_long(const int64_t *__restrict
     }
 }
 
+// Rows of each light tile ordered by degree (heavy rows, which the light kernel skips, count as 0),
+// stably: perm[tile * kTileRows + position] = row.  A wave of the light kernel then takes four rows of
+// about the same length, so fewer of its lanes wait for the longest.  Used on graphs whose light rows'
+// degrees vary widely (see pspec_graph_create).
+__global__ __launch_bounds__(kTileRows) void k_tile_sort(const int64_t *__restrict__ rowptr, int64_t n,
+                                                       int light_max, int32_t *__restrict__ perm) {
+    __shared__ int s_key[kTileRows];
+    const int t = threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.x * kTileRows + t;
+    int key = light_max + 1;  // past the last row: sorts last, not written
+    if (row < n) {
+        const int64_t d = rowptr[row + 1] - rowptr[row];
+        key = d <= light_max ? (int)d : 0;
+    }
+    s_key[t] = key;
+    __syncthreads();
+    int pos = 0;
+    for (int u = 0; u < kTileRows; ++u) {
+        const int ku = s_key[u];
+        pos += (ku < key) || (ku == key && u < t);
+    }
+    if (row < n) perm[(int64_t)blockIdx.x * kTileRows + pos] = (int32_t)row;
+}
+
 // Column segment boundaries: bound[s] = the first node j with rowptr[j] >= s nnz / kSegs, so each
 // segment [bound[s], bound[s + 1]) holds an equal share of the stored entries -- and, the graph being
 // symmetric, receives an equal share of the neighbour gathers.  One thread per boundary.
@@ -200,7 +226,12 @@ __device__ __forceinline__ void row_counts(const int64_t *__restrict__ rowptr, c
     for (int q = 0; q < kCounters; ++q) cnt[q] = 0;
     if (i >= n) return;
     const int64_t beg = rowptr[i], end = rowptr[i + 1], d = end - beg;
-    if (d <= light_max) return;
+    if (d <= light_max) {
+        cnt[kCLight] = 1;
+        cnt[kCDeg] = d;
+        cnt[kCDeg2] = d * d;
+        return;
+    }
     cnt[kCHeavy] = 1;
     if (d <= chunk) {
         cnt[kCGlob] = 1;
@@ -344,8 +375,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   chunks       <= heavy rows + split chunks
 //   partial rows  = light tiles + kHeavyGridCap
 struct WsLayout {
-    size_t bcount = 0, tot = 0, bound = 0, ust = 0, part = 0, red1 = 0, sc = 0, gram = 0, chunks = 0, splits = 0,
-           scr = 0;
+    size_t bcount = 0, tot = 0, bound = 0, ust = 0, perm = 0, part = 0, red1 = 0, sc = 0, gram = 0, chunks = 0,
+           splits = 0, scr = 0;
     size_t fixed = 0, total = 0;
 };
 
@@ -358,6 +389,7 @@ WsLayout ws_layout(int64_t n, int k_max, int64_t n_chunks, int64_t n_split, int6
         align256(sizeof(int64_t) * kCounters + sizeof(int)),
         align256(sizeof(int32_t) * (kSegs + 1)),
         align256(sizeof(int64_t) * (size_t)n),
+        align256(sizeof(int32_t) * (size_t)n),
         align256(sizeof(double) * (size_t)(tiles + kHeavyGridCap) * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kReduceSlices * kQ * (size_t)k_max),
         align256(sizeof(double) * (size_t)kScalars * (size_t)k_max),
@@ -366,12 +398,13 @@ WsLayout ws_layout(int64_t n, int k_max, int64_t n_chunks, int64_t n_split, int6
         align256(sizeof(Split) * (size_t)n_split),
         align256(sizeof(double) * (size_t)n_split_chunks * 2 * (size_t)k_max),
     };
-    size_t *dst[] = {&L.bcount, &L.tot, &L.bound, &L.ust, &L.part, &L.red1, &L.sc, &L.gram, &L.chunks, &L.splits, &L.scr};
+    size_t *dst[] = {&L.bcount, &L.tot,  &L.bound, &L.ust,    &L.perm,   &L.part,
+                     &L.red1,   &L.sc,   &L.gram,  &L.chunks, &L.splits, &L.scr};
     size_t off = 0;
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < 12; ++i) {
         *dst[i] = off;
         off += parts[i];
-        if (i == 7) L.fixed = off;
+        if (i == 8) L.fixed = off;
     }
     L.total = off;
     return L;
@@ -547,6 +580,20 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->ascending = (plan.flag & 4) == 0;
     g->ustart = reinterpret_cast<const int64_t *>(mem + L.ust);
     g->gram_part = pad_k(k_max) >= kGramK ? reinterpret_cast<double *>(mem + L.gram) : nullptr;
+    // Order each light tile's rows by degree when the light rows' degrees vary widely (coefficient of
+    // variation above 1: power-law graphs such as R-MAT, 1.4-1.9; SBM, kNN, grids and triangulations
+    // 0.04-0.3).  Rows of equal length then share a wave; on graphs of near-uniform degree the node
+    // order is kept, since it keeps each wave's row writes contiguous.
+    {
+        const double cntl = (double)plan.tot[kCLight], s1 = (double)plan.tot[kCDeg], s2 = (double)plan.tot[kCDeg2];
+        const double mean = cntl > 0 ? s1 / cntl : 0.0, var = cntl > 0 ? s2 / cntl - mean * mean : 0.0;
+        g->sorted_tiles = mean > 0.0 && var > mean * mean;
+    }
+    if (g->sorted_tiles) {
+        int32_t *perm = reinterpret_cast<int32_t *>(mem + L.perm);
+        k_tile_sort<<<(unsigned)g->tiles, kTileRows, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, perm);
+        g->lperm = perm;
+    }
     if (g->n_chunks > 0) {
         const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;
         k_plan_emit<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, reinterpret_cast<const int32_t *>(mem + L.bound),
