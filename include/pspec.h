@@ -157,6 +157,13 @@ pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int64_t *chunk
  * With ascending rows pspec_objective visits each undirected edge once (see there). */
 pspec_status pspec_graph_ascending(pspec_graph g, int *ascending);
 
+/* *on (host int) = 1 if the light kernel takes each 256-row tile's rows in order of degree, else 0
+ * (node order).  pspec_graph_create chooses degree order when the degrees of the rows of at most
+ * PSPEC_LIGHT_MAX entries have a coefficient of variation above 1 (power-law graphs), so that the
+ * rows sharing a wavefront are about equally long; on graphs of near-uniform degree node order keeps
+ * the row writes contiguous.  Results do not depend on the choice beyond summation order. */
+pspec_status pspec_graph_degree_order(pspec_graph g, int *on);
+
 /*
  * pspec_rcm_order -- a locality relabelling of the graph for the edge pass (the vxm of Section 2
  * gathers one neighbour row per edge; graphs numbered without locality, such as triangulations of

@@ -115,50 +115,40 @@ __global__ __launch_bounds__(kBlock) void k_upper(const int64_t *__restrict__ ro
 __global__ __launch_bounds__(kBlock) void k_upper_long(const int64_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col, int64_t n,
                                                      int64_t *__restrict__ ustart, int *__restrict__ flag) {
-    __shared__ int32_t s_list[kBlock];
-    __shared__ int s_cnt;
     __shared__ int64_t s_low[kBlock / 64];
     __shared__ int s_bad[kBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
-        // the long rows among base .. base + kBlock - 1 (listed in any order: each is handled once)
-        if (tid == 0) s_cnt = 0;
-        __syncthreads();
-        const int64_t r = base + tid;
-        if (r < n && rowptr[r + 1] - rowptr[r] > kUpperShort) s_list[atomicAdd(&s_cnt, 1)] = tid;
-        __syncthreads();
-        const int cnt = s_cnt;
-        for (int li = 0; li < cnt; ++li) {
-            const int64_t i = base + s_list[li];
-            const int64_t beg = rowptr[i], end = rowptr[i + 1];
-            int64_t low = 0;
-            int bad = 0;
-            for (int64_t q = beg + tid; q < end; q += kBlock) {
-                const int32_t c = col[q];
-                low += c <= (int32_t)i;
-                if (q + 1 < end && col[q + 1] < c) bad = 1;
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
-            const bool wbad = __any(bad);
-            if (lane == 0) {
-                s_low[w] = low;
-                s_bad[w] = wbad ? 1 : 0;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int64_t tot = 0;
-                int b = 0;
-                for (int v = 0; v < kBlock / 64; ++v) {
-                    tot += s_low[v];
-                    b |= s_bad[v];
-                }
-                ustart[i] = beg + tot;
-                if (b) atomicOr(flag, 4);
-            }
-            __syncthreads();
+    // workgroup b takes rows b, b + grid, ...: long rows, which cluster at the ids of hubs, spread
+    // over the whole grid
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t beg = rowptr[i], end = rowptr[i + 1];  // uniform over the workgroup
+        if (end - beg <= kUpperShort) continue;
+        int64_t low = 0;
+        int bad = 0;
+        for (int64_t q = beg + tid; q < end; q += kBlock) {
+            const int32_t c = col[q];
+            low += c <= (int32_t)i;
+            if (q + 1 < end && col[q + 1] < c) bad = 1;
         }
-        __syncthreads();  // s_cnt and s_list are reused by the next range
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
+        const bool wbad = __any(bad);
+        if (lane == 0) {
+            s_low[w] = low;
+            s_bad[w] = wbad ? 1 : 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t tot = 0;
+            int bb = 0;
+            for (int v = 0; v < kBlock / 64; ++v) {
+                tot += s_low[v];
+                bb |= s_bad[v];
+            }
+            ustart[i] = beg + tot;
+            if (bb) atomicOr(flag, 4);
+        }
+        __syncthreads();
     }
 }
 
@@ -473,8 +463,7 @@ pspec_status plan_counts(const char *who, int64_t n, int64_t nnz, const int64_t 
         const int64_t want = (n + kBlock / 16 - 1) / (kBlock / 16);
         k_upper<<<(unsigned)(want < 65536 ? want : 65536), kBlock, 0, s>>>(
             rowptr, col, n, reinterpret_cast<int64_t *>(mem + L.ust), flag);
-        const int64_t wl = (n + kBlock - 1) / kBlock;
-        k_upper_long<<<(unsigned)(wl < 65536 ? wl : 65536), kBlock, 0, s>>>(
+        k_upper_long<<<(unsigned)(n < 65536 ? n : 65536), kBlock, 0, s>>>(
             rowptr, col, n, reinterpret_cast<int64_t *>(mem + L.ust), flag);
     }
     k_plan_count<<<(unsigned)nb, kPlanBlock, 0, s>>>(rowptr, col, bound, n, PSPEC_LIGHT_MAX, PSPEC_CHUNK, bcount);
@@ -631,6 +620,14 @@ extern "C" pspec_status pspec_graph_ascending(pspec_graph g, int *ascending) {
     PSPEC_ARG(g != nullptr, "graph_ascending: NULL handle");
     PSPEC_ARG(ascending != nullptr, "graph_ascending: ascending is NULL");
     *ascending = g->ascending ? 1 : 0;
+    return PSPEC_OK;
+}
+
+extern "C" pspec_status pspec_graph_degree_order(pspec_graph g, int *on) {
+    clear_error();
+    PSPEC_ARG(g != nullptr, "graph_degree_order: NULL handle");
+    PSPEC_ARG(on != nullptr, "graph_degree_order: on is NULL");
+    *on = g->sorted_tiles ? 1 : 0;
     return PSPEC_OK;
 }
 

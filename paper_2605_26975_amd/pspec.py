@@ -53,6 +53,7 @@ def lib() -> ctypes.CDLL:
         "pspec_graph_destroy": [vp],
         "pspec_graph_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "pspec_graph_ascending": [vp, ctypes.POINTER(i32)],
+        "pspec_graph_degree_order": [vp, ctypes.POINTER(i32)],
         "pspec_graph_set_timing_events": [vp, vp, vp],
         "pspec_objective": [vp, i32, i32, vp, i64, dbl, vp, vp, vp],
         "pspec_grad": [vp, i32, i32, vp, i64, dbl, vp, i64, vp, vp],
@@ -94,6 +95,7 @@ def exported_symbols() -> list[str]:
     return [
         "pspec_graph_workspace_bytes", "pspec_graph_count_workspace_bytes", "pspec_graph_exact_workspace",
         "pspec_graph_create", "pspec_graph_destroy", "pspec_graph_info", "pspec_graph_ascending",
+        "pspec_graph_degree_order",
         "pspec_graph_set_timing_events",
         "pspec_objective", "pspec_grad",
         "pspec_hvp", "pspec_hvp_sparse", "pspec_hvp_gather_floor", "pspec_rhvp", "pspec_rhvp_static", "pspec_rhess", "pspec_dense_workspace_bytes", "pspec_project", "pspec_retract", "pspec_dot",
@@ -226,9 +228,11 @@ class Graph:
     def info(self) -> dict:
         h, c, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().pspec_graph_info(self.handle, ctypes.byref(h), ctypes.byref(c), ctypes.byref(s)))
-        a = ctypes.c_int()
+        a, o = ctypes.c_int(), ctypes.c_int()
         _check(lib().pspec_graph_ascending(self.handle, ctypes.byref(a)))
-        return dict(heavy_rows=h.value, chunks=c.value, split_rows=s.value, ascending=bool(a.value))
+        _check(lib().pspec_graph_degree_order(self.handle, ctypes.byref(o)))
+        return dict(heavy_rows=h.value, chunks=c.value, split_rows=s.value, ascending=bool(a.value),
+                    degree_order=bool(o.value))
 
     def set_timing_events_raw(self, before, after) -> None:
         """Record two raw hipEvent_t handles (or None, None) around the edge pass of later calls."""

@@ -98,11 +98,31 @@ def test_heavy_and_split_rows(k):
 
 @pytest.mark.parametrize("layout", ["separate", "interleaved"])
 def test_rmat_scale14_p105(layout):
-    """Skewed degrees (R-MAT), k = 32, p = 1.05, eps = 1e-8."""
+    """Skewed degrees (R-MAT), k = 32, p = 1.05, eps = 1e-8; the light tiles in degree order."""
     print(f"[case] rmat14 {layout}", flush=True)
     g = gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9)
-    gu.check(gu.compare(g, 32, 1.05, 1e-8, torch.float32, layout=layout), torch.float32)
-    gu.check(gu.compare(g, 32, 1.05, 1e-8, torch.float64), torch.float64)
+    dg = gu.device_graph(g, 32)
+    assert dg.info()["degree_order"]
+    gu.check(gu.compare(g, 32, 1.05, 1e-8, torch.float32, dg=dg, layout=layout), torch.float32)
+    gu.check(gu.compare(g, 32, 1.05, 1e-8, torch.float64, dg=dg), torch.float64)
+
+
+def test_degree_order_rule():
+    """The light tiles take degree order exactly when the degrees of the light rows (at most
+    LIGHT_MAX entries) have a coefficient of variation above 1, recomputed here in NumPy."""
+    graphs = [gen.sbm_bernoulli(1000, 4, 0.05, 0.002), gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9),
+              gen.rmat(12, 8, 0.57, 0.19, 0.19, 0.1, 1.0, seed=3), _hub_graph(), gen.grid3d(16),
+              gen.knn_mixture(5_000, 4, 10, 1.0, 20.0, seed=4)]
+    seen = set()
+    for g in graphs:
+        d = g.degrees()
+        light = d[d <= pspec.LIGHT_MAX].astype(np.float64)
+        want = bool(light.mean() > 0 and light.var() > light.mean() ** 2)
+        got = gu.device_graph(g, 4).info()["degree_order"]
+        print(f"{g.name}: cv {light.std() / light.mean():.2f} degree order {got}", flush=True)
+        assert got == want
+        seen.add(got)
+    assert seen == {True, False}
 
 
 def test_knn_graph_p13():
