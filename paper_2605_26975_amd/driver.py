@@ -183,12 +183,12 @@ def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | Non
     U = pspec.axpby(1.0, U, 0.0, torch.empty_like(U))  # working copy
     Heta = torch.empty_like(U)
     g0 = None
+    Fu = s.F(U, p)  # kept from the accepted trial point afterwards: every F here is one objective call
     for it in range(opt.max_outer):
         pspec.grad(s.graph, U, p, G=s.G)
         pspec.project(U, s.G, out=s.rgrad, M=s.MG)
         gg = s.dot(s.rgrad, s.rgrad)
         gn = gg ** 0.5
-        Fu = s.F(U, p)
         info.F.append(Fu)
         info.grad_norm.append(gn)
         if g0 is None:
@@ -238,11 +238,13 @@ def rtr(solver: Solver, U: torch.Tensor, p: float, opt: TrustRegionOptions | Non
             delta *= 0.25
         elif rho > 0.75 and eta_norm >= 0.99 * delta:
             delta = min(2.0 * delta, delta_bar)
+        F_it = Fu
         if rho > opt.rho_accept:
             pspec.axpby(1.0, s.Ut, 0.0, U)
+            Fu = Ft
         info.iterations = it + 1
         if progress is not None:
-            progress(it + 1, Fu, gn, nt)
+            progress(it + 1, F_it, gn, nt)
     return U, info
 
 
