@@ -258,9 +258,12 @@ __device__ __forceinline__ T edge_bcast_val(T v, int e, int lane) {
 // the chunk's neighbour ids and weights with one coalesced load (lane l takes edge l), the loading
 // lane turns each id into byte offsets into U and V once, DPP row broadcasts hand offsets and
 // weights to the lanes that need them, and every gather of the chunk is issued before any is
-// used.  The group's next row (its own u_i, v_i and first-chunk ids) is loaded before the current
-// row's gathers.  The gather rate of random neighbour rows, not HBM bandwidth, bounds this kernel
-// on random graphs: rows in flight per wave matter more than the width of each load.
+// used (in FP32; FP64 issues them in batches, see light_batches).  The group's next row (its own
+// u_i, v_i and first-chunk ids) is loaded before the current row's gathers.  A tile's rows are taken
+// in node order, or in degree order (lperm) on graphs whose light rows' degrees vary widely, so that
+// the four rows of a wave are about equally long.  The gather rate of random neighbour rows, not
+// HBM bandwidth, bounds this kernel on random graphs: rows in flight per wave matter more than the
+// width of each load.
 template <int K>
 constexpr int light_cpl() {
     return K > 16 ? K / 16 : 1;

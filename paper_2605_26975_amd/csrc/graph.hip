@@ -1,9 +1,12 @@
 // Graph handle: CSR validation and the degree-binned row schedule.
 //
-// Rows with at most PSPEC_LIGHT_MAX neighbours are processed in node order by the light edge
-// kernel (a group of lanes per row, kTileRows rows per workgroup).  Longer rows are cut into
-// chunks of at most PSPEC_CHUNK edges, handed in a fixed order to the waves of the persistent
-// heavy-chunk kernel; rows with several chunks are summed afterwards in chunk order.  The schedule is
+// Rows with at most PSPEC_LIGHT_MAX neighbours are processed by the light edge kernel (a group of
+// lanes per row, kTileRows rows per workgroup), in node order or, on graphs whose light rows' degrees
+// vary widely, in degree order within each tile.  Longer rows are cut into chunks of at most
+// PSPEC_CHUNK edges (rows above PSPEC_CHUNK first at the kSegs column-segment boundaries), handed in
+// a fixed order to the waves of the persistent heavy-chunk kernel; rows with several chunks are
+// summed afterwards in chunk order.  Each row's first entry above the diagonal is recorded for the
+// edge-once objective.  The schedule is
 // built with three integer kernels (per-block counts, one-block exclusive scan, per-block emission
 // with a block-local scan), so chunk order, and with it every floating-point sum, is the same on every
 // run.  Everything the handle keeps on the device lives in the caller's workspace, whose size is
