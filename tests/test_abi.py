@@ -161,6 +161,9 @@ def test_graph_workspace_bound_covers_every_schedule():
     worst_chunks = max(n, -(-nnz // chunk) + 8)
     assert base >= 24 * worst_chunks + 2 * 8 * 8 * (-(-nnz // chunk) + 8)
     assert f(n, 0, 8) > 0  # an empty graph still needs its partial sums
+    # k_max > 8 adds the Gram area of the Riemannian call (one 4 x 16 x 16 FP64 partial per 256-row
+    # tile and per heavy-row workgroup, plus the rows of its fixed-order reduction)
+    assert f(n, nnz, 9) - f(n, nnz, 8) >= 8192 * (-(-n // 256) + 256 + 1024 + 32 + 1)
 
 
 def test_binding_rejects_mismatched_blocks(monkeypatch):
