@@ -129,15 +129,17 @@ pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *
  *                   validating the CSR and to read back the sizes of the schedule.
  *   out             receives the handle (a small host object).
  * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
- * 16-lane group per row in node order; rows of up to PSPEC_CHUNK edges are one chunk each, handed
+ * 16-lane group per row, in node order or in degree order within each 256-row tile (see
+ * pspec_graph_degree_order); rows of up to PSPEC_CHUNK edges are one chunk each, handed
  * out in a fixed order to one wavefront each; longer rows are cut at 8 column-segment boundaries
  * (node-id ranges holding equal shares of the stored entries) and each piece into chunks of at
  * most PSPEC_CHUNK edges, the chunks of segment s going to the workgroups that run on XCD s, and
  * such rows are combined in a fixed order afterwards, so every result is bit-reproducible.  Any
  * column order within a row is valid; ascending columns (the usual CSR) let each XCD's L2 cache
- * the neighbour rows of one segment only.  The CSR is
- * validated on the device (rowptr monotone with rowptr[0] = 0 and rowptr[n] = nnz, every column
- * in [0, n)); a malformed graph returns PSPEC_ERR_ARG.  No device memory is allocated.
+ * the neighbour rows of one segment only, and let pspec_objective visit each undirected edge once
+ * (pspec_graph_ascending).  The CSR is validated on the device (rowptr monotone with
+ * rowptr[0] = 0 and rowptr[n] = nnz, every column in [0, n)); a malformed graph returns
+ * PSPEC_ERR_ARG.  No device memory is allocated.
  */
 #define PSPEC_LIGHT_MAX 32
 #define PSPEC_CHUNK 512
