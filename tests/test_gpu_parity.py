@@ -107,6 +107,23 @@ def test_rmat_scale14_p105(layout):
     gu.check(gu.compare(g, 32, 1.05, 1e-8, torch.float64, dg=dg), torch.float64)
 
 
+@pytest.mark.parametrize("k", [16, 32])
+def test_degree_order_ragged_last_tile(k):
+    """Degree order with a ragged last tile (n = 16,284, not a multiple of 256): the fused grad+HVP
+    and the edge-once objective against the oracle, every entry within its bound."""
+    print(f"[case] degree order ragged k={k}", flush=True)
+    full = gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9)
+    keep = np.ones(full.n, dtype=bool)
+    keep[-100:] = False
+    g, _ = gen.induced(full, keep, "rmat14-ragged")
+    assert g.n % 256 != 0
+    dg = gu.device_graph(g, k)
+    info = dg.info()
+    assert info["degree_order"] and info["ascending"] and info["split_rows"] > 0
+    gu.check(gu.compare(g, k, 1.05, 1e-8, torch.float32, dg=dg, layout="interleaved"), torch.float32)
+    gu.check(gu.compare(g, k, 1.05, 1e-8, torch.float64, dg=dg), torch.float64)
+
+
 def test_degree_order_rule():
     """The light tiles take degree order exactly when the degrees of the light rows (at most
     LIGHT_MAX entries) have a coefficient of variation above 1, recomputed here in NumPy."""
