@@ -129,8 +129,9 @@ pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *
  *                   validating the CSR and to read back the sizes of the schedule.
  *   out             receives the handle (a small host object).
  * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
- * 16-lane group per row, in node order or in degree order within each 256-row tile (see
- * pspec_graph_degree_order); rows of up to PSPEC_CHUNK edges are one chunk each, handed
+ * 16-lane group per row, in node order or in degree order within each 256-row tile (FP64 calls
+ * always in degree order; see pspec_graph_degree_order); rows of up to PSPEC_CHUNK edges are one
+ * chunk each, handed
  * out in a fixed order to one wavefront each; longer rows are cut at 8 column-segment boundaries
  * (node-id ranges holding equal shares of the stored entries) and each piece into chunks of at
  * most PSPEC_CHUNK edges, the chunks of segment s going to the workgroups that run on XCD s, and
@@ -159,11 +160,13 @@ pspec_status pspec_graph_info(pspec_graph g, int64_t *heavy_rows, int64_t *chunk
  * With ascending rows pspec_objective visits each undirected edge once (see there). */
 pspec_status pspec_graph_ascending(pspec_graph g, int *ascending);
 
-/* *on (host int) = 1 if the light kernel takes each 256-row tile's rows in order of degree, else 0
- * (node order).  pspec_graph_create chooses degree order when the degrees of the rows of at most
- * PSPEC_LIGHT_MAX entries have a coefficient of variation above 1 (power-law graphs), so that the
- * rows sharing a wavefront are about equally long; on graphs of near-uniform degree node order keeps
- * the row writes contiguous.  Results do not depend on the choice beyond summation order. */
+/* *on (host int) = 1 if FP32 calls take each 256-row tile's light rows in order of degree, else 0
+ * (node order).  pspec_graph_create chooses degree order for FP32 when the degrees of the rows of at
+ * most PSPEC_LIGHT_MAX entries have a coefficient of variation above 1 (power-law graphs), so that
+ * the rows sharing a wavefront are about equally long; on graphs of near-uniform degree node order
+ * keeps the row writes contiguous, which counts for more in the gather-bound FP32 pass.  FP64 calls,
+ * bound by the arithmetic, take degree order on every graph.  Results do not depend on the order
+ * beyond summation order. */
 pspec_status pspec_graph_degree_order(pspec_graph g, int *on);
 
 /*

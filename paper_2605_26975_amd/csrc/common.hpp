@@ -100,8 +100,9 @@ struct Graph {
     bool ascending = false;
     const int64_t *ustart = nullptr;  // device [n]
     double *gram_part = nullptr;      // device [gram_area_rows(tiles)][kGramQ * kGramK^2] (k_max > 8), else NULL
-    // Light tiles' rows ordered by degree (graphs whose light-row degrees vary widely): the light
-    // kernel takes row lperm[tile * kTileRows + slot] in slot order; NULL: node order.
+    // Light tiles' rows ordered by degree: the light kernel takes row lperm[tile * kTileRows + slot]
+    // in slot order (NULL: no light rows).  FP64 calls always use it; FP32 calls only when
+    // sorted_tiles (light-row degrees vary widely), else node order.
     bool sorted_tiles = false;
     const int32_t *lperm = nullptr;   // device [n]
     hipEvent_t ev_before = nullptr, ev_after = nullptr;  // optional edge-pass timing events

@@ -260,10 +260,10 @@ __device__ __forceinline__ T edge_bcast_val(T v, int e, int lane) {
 // weights to the lanes that need them, and every gather of the chunk is issued before any is
 // used (in FP32; FP64 issues them in batches, see light_batches).  The group's next row (its own
 // u_i, v_i and first-chunk ids) is loaded before the current row's gathers.  A tile's rows are taken
-// in node order, or in degree order (lperm) on graphs whose light rows' degrees vary widely, so that
-// the four rows of a wave are about equally long.  The gather rate of random neighbour rows, not
-// HBM bandwidth, bounds this kernel on random graphs: rows in flight per wave matter more than the
-// width of each load.
+// in degree order (lperm), so that the four rows of a wave are about equally long, in every FP64 call
+// and in FP32 calls on graphs whose light rows' degrees vary widely; else in node order.  The
+// gather rate of random neighbour rows, not HBM bandwidth, bounds this kernel in FP32 on random
+// graphs: rows in flight per wave matter more than the width of each load.
 template <int K>
 constexpr int light_cpl() {
     return K > 16 ? K / 16 : 1;
@@ -1031,7 +1031,7 @@ pspec_status edge_pass(Graph *g, int k, const T *U, int64_t ldu, const T *V, int
     a.n_chunks = g->n_chunks;
     a.ustart = (MODE == OBJ && g->ascending) ? g->ustart : nullptr;
     a.gpart = GRAM ? g->gram_part : nullptr;
-    a.lperm = g->lperm;
+    a.lperm = (sizeof(T) == 8 || g->sorted_tiles) ? g->lperm : nullptr;
     if (g->ev_before) PSPEC_HIP(hipEventRecord(g->ev_before, s));
     edge_light<T, WT, K, MODE, FLOOR, GRAM><<<(unsigned)g->tiles, kBlock, 0, s>>>(a);
     const int64_t hb = heavy_grid<T, WT, K>(g);

@@ -157,8 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_upper_long(const int64_t *__restrict
 
 // Rows of each light tile ordered by degree (heavy rows, which the light kernel skips, count as 0),
 // stably: perm[tile * kTileRows + position] = row.  A wave of the light kernel then takes four rows of
-// about the same length, so fewer of its lanes wait for the longest.  Used on graphs whose light rows'
-// degrees vary widely (see pspec_graph_create).
+// about the same length, so fewer of its lanes wait for the longest.  Used by every FP64 call, and by
+// FP32 calls on graphs whose light rows' degrees vary widely (see pspec_graph_create).
 __global__ __launch_bounds__(kTileRows) void k_tile_sort(const int64_t *__restrict__ rowptr, int64_t n,
                                                        int light_max, int32_t *__restrict__ perm) {
     __shared__ int s_key[kTileRows];
@@ -572,19 +572,20 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->ascending = (plan.flag & 4) == 0;
     g->ustart = reinterpret_cast<const int64_t *>(mem + L.ust);
     g->gram_part = pad_k(k_max) >= kGramK ? reinterpret_cast<double *>(mem + L.gram) : nullptr;
-    // Order each light tile's rows by degree when the light rows' degrees vary widely (coefficient of
-    // variation above 1: power-law graphs such as R-MAT, 1.4-1.9; SBM, kNN, grids and triangulations
-    // 0.04-0.3).  Rows of equal length then share a wave; on graphs of near-uniform degree the node
-    // order is kept, since it keeps each wave's row writes contiguous.
+    // Each light tile's rows in degree order, so that rows of equal length share a wave.  FP64 calls,
+    // bound by the arithmetic of the power, always take this order.  FP32 calls, bound by the gathers,
+    // take it only when the light rows' degrees vary widely (coefficient of variation above 1:
+    // power-law graphs such as R-MAT, 1.4-1.9; SBM, kNN, grids and triangulations 0.04-0.3); on graphs
+    // of near-uniform degree they keep the node order, which keeps each wave's row writes contiguous.
     {
         const double cntl = (double)plan.tot[kCLight], s1 = (double)plan.tot[kCDeg], s2 = (double)plan.tot[kCDeg2];
         const double mean = cntl > 0 ? s1 / cntl : 0.0, var = cntl > 0 ? s2 / cntl - mean * mean : 0.0;
         g->sorted_tiles = mean > 0.0 && var > mean * mean;
-    }
-    if (g->sorted_tiles) {
-        int32_t *perm = reinterpret_cast<int32_t *>(mem + L.perm);
-        k_tile_sort<<<(unsigned)g->tiles, kTileRows, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, perm);
-        g->lperm = perm;
+        if (mean > 0.0) {
+            int32_t *perm = reinterpret_cast<int32_t *>(mem + L.perm);
+            k_tile_sort<<<(unsigned)g->tiles, kTileRows, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, perm);
+            g->lperm = perm;
+        }
     }
     if (g->n_chunks > 0) {
         const int64_t nb = (n + kPlanBlock - 1) / kPlanBlock;

@@ -124,9 +124,25 @@ def test_degree_order_ragged_last_tile(k):
     gu.check(gu.compare(g, k, 1.05, 1e-8, torch.float64, dg=dg), torch.float64)
 
 
+def test_fp64_degree_order_on_uniform_graph():
+    """Near-uniform degrees (SBM, n = 3,000, a ragged last tile): FP32 calls keep node order, FP64
+    calls take degree order, both from the same handle; grad+HVP, objective and the Riemannian call
+    against the oracle, every entry within its bound."""
+    print("[case] fp64 degree order sbm3000", flush=True)
+    g = gen.sbm_bernoulli(3000, 3, 0.01, 0.001, seed=21)
+    assert g.n % 256 != 0
+    d = g.degrees()
+    assert d.max() <= pspec.LIGHT_MAX and d.std() < d.mean()
+    dg = gu.device_graph(g, 16)
+    assert not dg.info()["degree_order"]
+    for dtype in (torch.float64, torch.float32):
+        gu.check(gu.compare(g, 16, 1.1, 1e-8, dtype, dg=dg), dtype)
+
+
 def test_degree_order_rule():
-    """The light tiles take degree order exactly when the degrees of the light rows (at most
-    LIGHT_MAX entries) have a coefficient of variation above 1, recomputed here in NumPy."""
+    """FP32 calls take the light tiles in degree order exactly when the degrees of the light rows
+    (at most LIGHT_MAX entries) have a coefficient of variation above 1, recomputed here in NumPy
+    (FP64 calls take degree order on every graph)."""
     graphs = [gen.sbm_bernoulli(1000, 4, 0.05, 0.002), gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9),
               gen.rmat(12, 8, 0.57, 0.19, 0.19, 0.1, 1.0, seed=3), _hub_graph(), gen.grid3d(16),
               gen.knn_mixture(5_000, 4, 10, 1.0, 20.0, seed=4)]
