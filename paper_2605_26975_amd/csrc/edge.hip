@@ -270,11 +270,17 @@ constexpr int light_cpl() {
 }
 
 // Batches in which the light kernel issues and consumes the gathers of one chunk of G edges: all at
-// once in FP32, whose pass is bound by the gathers; in 2 (k <= 16) or 4 batches in FP64, whose pass
-// is bound by the arithmetic of the power and gains resident waves from the registers this frees.
-template <typename T, int K>
+// once in FP32, whose pass is bound by the gathers; in several batches in FP64, whose pass is bound
+// by the arithmetic of the power and gains resident waves from the registers this frees.  Measured
+// per mode and width: the objective 4 at k >= 16 (k = 16: 6 -> 7 waves per SIMD) and 2 below (4
+// measured slower on a 100k-node kNN graph, k = 8, whose few waves gain nothing from occupancy); the
+// gradient passes 2 at k <= 16 (4 waves either way, fewer waits), 8 at k = 32 (3 -> 4 waves) and 4
+// above.
+template <typename T, int K, int MODE>
 constexpr int light_batches() {
-    return sizeof(T) == 8 ? (K >= 32 ? 4 : 2) : 1;
+    if constexpr (sizeof(T) == 4) return 1;
+    else if constexpr (MODE == OBJ) return K >= 16 ? 4 : 2;
+    else return K == 32 ? 8 : (K > 32 ? 4 : 2);
 }
 
 // Waves per SIMD the light kernel is compiled for (k = 32 in FP32 sits just above 128 VGPRs).
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
                     wl2 = (T)a.w[c1 + gl];
                 }
             }
-            constexpr int NBAT = light_batches<T, K>();
+            constexpr int NBAT = light_batches<T, K, MODE>();
             constexpr int BU = NU / NBAT;
             static_for<0, NBAT>([&](auto bc) {
                 constexpr int b0 = decltype(bc)::value * BU;

@@ -156,18 +156,23 @@ __global__ __launch_bounds__(kBlock) void k_upper_long(const int64_t *__restrict
 }
 
 // Rows of each light tile ordered by degree (heavy rows, which the light kernel skips, count as 0),
-// stably: perm[tile * kTileRows + position] = row.  A wave of the light kernel then takes four rows of
-// about the same length, so fewer of its lanes wait for the longest.  Used by every FP64 call, and by
-// FP32 calls on graphs whose light rows' degrees vary widely (see pspec_graph_create).
-__global__ __launch_bounds__(kTileRows) void k_tile_sort(const int64_t *__restrict__ rowptr, int64_t n,
+// and rows of equal degree by their number of entries above the diagonal (ustart, when the columns
+// ascend), stably: perm[tile * kTileRows + position] = row.  A wave of the light kernel then takes
+// four rows of about the same length, so fewer of its lanes wait for the longest: in the gradient
+// passes, which visit whole rows, and in the edge-once objective, which visits the entries above the
+// diagonal.  Used by every FP64 call, and by FP32 calls on graphs whose light rows' degrees vary
+// widely (see pspec_graph_create).
+__global__ __launch_bounds__(kTileRows) void k_tile_sort(const int64_t *__restrict__ rowptr,
+                                                       const int64_t *__restrict__ ustart, int64_t n,
                                                        int light_max, int32_t *__restrict__ perm) {
     __shared__ int s_key[kTileRows];
     const int t = threadIdx.x;
     const int64_t row = (int64_t)blockIdx.x * kTileRows + t;
-    int key = light_max + 1;  // past the last row: sorts last, not written
+    int key = (light_max + 1) * (light_max + 1);  // past the last row: sorts last, not written
     if (row < n) {
-        const int64_t d = rowptr[row + 1] - rowptr[row];
-        key = d <= light_max ? (int)d : 0;
+        const int64_t e = rowptr[row + 1], d = e - rowptr[row];
+        const int64_t up = ustart != nullptr ? e - ustart[row] : 0;  // 0 <= up <= d
+        key = d <= light_max ? (int)(d * (light_max + 1) + up) : 0;
     }
     s_key[t] = key;
     __syncthreads();
@@ -572,8 +577,9 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
     g->ascending = (plan.flag & 4) == 0;
     g->ustart = reinterpret_cast<const int64_t *>(mem + L.ust);
     g->gram_part = pad_k(k_max) >= kGramK ? reinterpret_cast<double *>(mem + L.gram) : nullptr;
-    // Each light tile's rows in degree order, so that rows of equal length share a wave.  FP64 calls,
-    // bound by the arithmetic of the power, always take this order.  FP32 calls, bound by the gathers,
+    // Each light tile's rows in degree order (equal degrees by their count of entries above the
+    // diagonal), so that rows of equal length share a wave.  FP64 calls, bound by the arithmetic of
+    // the power, always take this order.  FP32 calls, bound by the gathers,
     // take it only when the light rows' degrees vary widely (coefficient of variation above 1:
     // power-law graphs such as R-MAT, 1.4-1.9; SBM, kNN, grids and triangulations 0.04-0.3); on graphs
     // of near-uniform degree they keep the node order, which keeps each wave's row writes contiguous.
@@ -583,7 +589,8 @@ extern "C" pspec_status pspec_graph_create(int64_t n, int64_t nnz, const int64_t
         g->sorted_tiles = mean > 0.0 && var > mean * mean;
         if (mean > 0.0) {
             int32_t *perm = reinterpret_cast<int32_t *>(mem + L.perm);
-            k_tile_sort<<<(unsigned)g->tiles, kTileRows, 0, s>>>(rowptr, n, PSPEC_LIGHT_MAX, perm);
+            k_tile_sort<<<(unsigned)g->tiles, kTileRows, 0, s>>>(rowptr, g->ascending ? g->ustart : nullptr, n,
+                                                                 PSPEC_LIGHT_MAX, perm);
             g->lperm = perm;
         }
     }

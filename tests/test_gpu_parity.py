@@ -356,6 +356,38 @@ def test_invalid_csr_and_arguments_are_rejected():
     assert torch.isfinite(F)
 
 
+def test_size_limits_are_rejected_before_any_launch():
+    """The documented limits: a block spanning 4 GiB or more (32-bit buffer offsets) and k_max above
+    PSPEC_K_MAX return PSPEC_ERR_UNSUPPORTED from the host checks.  The oversized blocks are real
+    small tensors given a leading dimension that makes their extent exceed 4 GiB, so nothing may be
+    launched on them; the calls are made through the C ABI to bypass the binding's own shape checks."""
+    import ctypes
+
+    g = gen.sbm_bernoulli(200, 2, 0.1, 0.01)
+    dg = gu.device_graph(g, 4)
+    lib = pspec.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+    for dt, dtype in ((0, torch.float32), (1, torch.float64)):
+        es = 4 if dt == 0 else 8
+        big = (1 << 32) // (es * (g.n - 1)) + 1  # (n - 1) * big * es >= 4 GiB
+        U = torch.randn(g.n, 4, dtype=dtype, device="cuda")
+        V = torch.randn(g.n, 4, dtype=dtype, device="cuda")
+        HV, G = torch.empty_like(U), torch.empty_like(U)
+        Fc = torch.empty(4, dtype=torch.float64, device="cuda")
+        HV0 = HV.clone()
+        for ldu, ldv in ((big, 4), (4, big)):
+            st = lib.pspec_hvp(dg.handle, dt, 4, U.data_ptr(), ldu, V.data_ptr(), ldv, 1.5, 1e-8, HV.data_ptr(), 4,
+                               G.data_ptr(), 4, Fc.data_ptr(), ctypes.c_void_p(stream))
+            assert st == 2, (dt, ldu, ldv, st)
+            assert b"4 GiB" in lib.pspec_last_error()
+        torch.cuda.synchronize()
+        assert torch.equal(HV, HV0)  # nothing was written
+    with pytest.raises(pspec.PSpecError) as ei:
+        gu.device_graph(g, pspec.K_MAX + 1)
+    assert ei.value.status in (1, 2)
+    dg.close()
+
+
 # --- Grassmann steps --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
