@@ -211,11 +211,13 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-// Value of lane IDX of this lane's group of G lanes (G in {16, 32, 64}), for 32-bit payloads.
+// Value of lane IDX of this lane's group of G lanes (G in {4, 16, 32, 64}), for 32-bit payloads.
 template <int G, int IDX>
 __device__ __forceinline__ int32_t group_bcast(int32_t v, int lane) {
     static_assert(IDX >= 0 && IDX < G, "lane index outside the group");
-    if constexpr (G == 16) {
+    if constexpr (G == 4) {
+        return __builtin_amdgcn_update_dpp(0, v, IDX * 0x55, 0xf, 0xf, false);  // DPP quad_perm [IDX x 4]
+    } else if constexpr (G == 16) {
         return __builtin_amdgcn_update_dpp(0, v, 0x150 + IDX, 0xf, 0xf, false);  // DPP row_newbcast
     } else if constexpr (G == 32) {
         const int32_t lo = __builtin_amdgcn_readlane(v, IDX);
@@ -250,23 +252,32 @@ __device__ __forceinline__ T edge_bcast_val(T v, int e, int lane) {
     }
 }
 
-// Light rows: a group of G = 16 lanes (one DPP row) per row, four rows per wave, kTileRows rows
-// per workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR
+// Light rows: a group of G = 16 lanes (one DPP row) per row, four rows per wave, or for k <= 4 a
+// group of G = 4 lanes (one DPP quad) per row, sixteen rows per wave; kTileRows rows per
+// workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR
 // ranges.  For k <= 16 the group is KL = K column lanes x G/KL edge slots; for k > 16 each lane
 // owns CPL = K/16 columns at stride 16, so every load is a coalesced 64-byte segment and four rows
 // per wave stay in flight whatever k is.  A row is walked in chunks of G edges: the group loads
 // the chunk's neighbour ids and weights with one coalesced load (lane l takes edge l), the loading
-// lane turns each id into byte offsets into U and V once, DPP row broadcasts hand offsets and
+// lane turns each id into byte offsets into U and V once, DPP broadcasts hand offsets and
 // weights to the lanes that need them, and every gather of the chunk is issued before any is
 // used (in FP32; FP64 issues them in batches, see light_batches).  The group's next row (its own
 // u_i, v_i and first-chunk ids) is loaded before the current row's gathers.  A tile's rows are taken
-// in degree order (lperm), so that the four rows of a wave are about equally long, in every FP64 call
+// in degree order (lperm), so that the rows of a wave are about equally long, in every FP64 call
 // and in FP32 calls on graphs whose light rows' degrees vary widely; else in node order.  The
 // gather rate of random neighbour rows, not HBM bandwidth, bounds this kernel in FP32 on random
 // graphs: rows in flight per wave matter more than the width of each load.
 template <int K>
 constexpr int light_cpl() {
     return K > 16 ? K / 16 : 1;
+}
+
+// Lanes per row group: 16, or 4 for k <= 4, where a 16-lane group would hold 4 edge slots of 4
+// columns and repeat the row's own power and sums in every slot; 4-lane groups take one edge at a
+// time and keep 16 rows per wave in flight.
+template <int K>
+constexpr int light_group() {
+    return K <= 4 ? 4 : 16;
 }
 
 // Batches in which the light kernel issues and consumes the gathers of one chunk of G edges: all at
@@ -291,7 +302,7 @@ constexpr int light_waves() {
 
 template <typename T, typename WT, int K, int MODE, bool FLOOR = false, bool GRAM = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_waves<T, K, GRAM>()))) void edge_light(EdgeArgs<T, WT> a) {
-    constexpr int G = 16;
+    constexpr int G = light_group<K>();  // lanes per row group
     constexpr int CPL = light_cpl<K>();  // columns per lane
     constexpr int KL = K / CPL;          // column lanes per edge slot
     constexpr int EPR = G / KL;          // edge slots per row
