@@ -81,8 +81,10 @@ def expected_chunks(g, segs=8):
     return total
 
 
-@pytest.mark.parametrize("k", [5, 32])
+@pytest.mark.parametrize("k", [4, 5, 32])
 def test_heavy_and_split_rows(k):
+    """Rows at and around LIGHT_MAX and CHUNK (light, single-chunk and split rows); k = 4 takes the
+    4-lane row groups, whose light rows of up to 32 edges span up to 8 chunks of 4."""
     print(f"[case] hubs k={k}", flush=True)
     g = _hub_graph()
     dg = gu.device_graph(g, k)
