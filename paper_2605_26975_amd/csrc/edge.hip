@@ -532,7 +532,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(light_wa
 // Heavy rows: chunks of at most PSPEC_CHUNK edges handed out in a fixed order to persistent waves.
 // Workgroup b first serves column segment s = b % kSegs (the XCD it runs on): its waves take that
 // segment's chunks in turn, so one XCD's L2 only ever holds neighbour rows of one segment; then every
-// wave W of the grid takes the shared list's chunks W, W + NW, W + 2 NW, ...  A wave stages its chunk's neighbour
+// wave W of the grid takes the shared list's chunks W, W + NW, W + 2 NW, ...  (The objective walks the
+// whole list that way, see below.)  A wave stages its chunk's neighbour
 // byte offsets and weights in its own slice of LDS (no workgroup barrier), runs ES = 64 / K edge
 // slots of K column lanes with UNR gathers in flight per lane (slots past the chunk gather the row
 // itself with weight 0, so every load is unconditional), adds the slots up with cross-lane sums,
@@ -654,14 +655,23 @@ __global__ __launch_bounds__(kBlock) void edge_heavy(EdgeArgs<T, WT> a) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    {  // this workgroup's column segment (gridDim.x is a multiple of kSegs)
-        const int sg = blockIdx.x % kSegs;
-        const int64_t step = (int64_t)(gridDim.x / kSegs) * NWB;
-        for (int64_t ci = a.seg_base[sg] + (int64_t)(blockIdx.x / kSegs) * NWB + wv; ci < a.seg_base[sg + 1]; ci += step)
-            chunk(ci);
-    }
     const int64_t NW = (int64_t)gridDim.x * NWB;
-    for (int64_t ci = a.seg_base[kSegs] + (int64_t)blockIdx.x * NWB + wv; ci < a.n_chunks; ci += NW) chunk(ci);
+    if constexpr (MODE == OBJ) {
+        // The objective visits only the entries above the diagonal, and the column segments hold
+        // very unequal shares of those (segment s keeps an entry only when its row id is below the
+        // column), so segment-bound workgroups would idle on the low segments: the whole chunk list
+        // is walked with one stride instead.
+        for (int64_t ci = (int64_t)blockIdx.x * NWB + wv; ci < a.n_chunks; ci += NW) chunk(ci);
+    } else {
+        {  // this workgroup's column segment (gridDim.x is a multiple of kSegs)
+            const int sg = blockIdx.x % kSegs;
+            const int64_t step = (int64_t)(gridDim.x / kSegs) * NWB;
+            for (int64_t ci = a.seg_base[sg] + (int64_t)(blockIdx.x / kSegs) * NWB + wv; ci < a.seg_base[sg + 1];
+                 ci += step)
+                chunk(ci);
+        }
+        for (int64_t ci = a.seg_base[kSegs] + (int64_t)blockIdx.x * NWB + wv; ci < a.n_chunks; ci += NW) chunk(ci);
+    }
     if (e == 0) {
         s_acc[wv][0][c] = Nacc;
         s_acc[wv][1][c] = Sacc;
