@@ -211,12 +211,18 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-// Value of lane IDX of this lane's group of G lanes (G in {4, 16, 32, 64}), for 32-bit payloads.
+// Value of lane IDX of this lane's group of G lanes (G in {4, 8, 16, 32, 64}), for 32-bit payloads.
 template <int G, int IDX>
 __device__ __forceinline__ int32_t group_bcast(int32_t v, int lane) {
     static_assert(IDX >= 0 && IDX < G, "lane index outside the group");
     if constexpr (G == 4) {
         return __builtin_amdgcn_update_dpp(0, v, IDX * 0x55, 0xf, 0xf, false);  // DPP quad_perm [IDX x 4]
+    } else if constexpr (G == 8) {
+        // lane IDX % 4 of each quad, then the other quad's copy by row_half_mirror (lane j of each
+        // 8 takes lane 7 - j); each lane keeps the copy from the quad that holds lane IDX
+        const int32_t y = __builtin_amdgcn_update_dpp(0, v, (IDX & 3) * 0x55, 0xf, 0xf, false);
+        const int32_t z = __builtin_amdgcn_update_dpp(0, y, 0x141, 0xf, 0xf, false);
+        return (lane & 4) == (IDX & 4) ? y : z;
     } else if constexpr (G == 16) {
         return __builtin_amdgcn_update_dpp(0, v, 0x150 + IDX, 0xf, 0xf, false);  // DPP row_newbcast
     } else if constexpr (G == 32) {
@@ -252,12 +258,12 @@ __device__ __forceinline__ T edge_bcast_val(T v, int e, int lane) {
     }
 }
 
-// Light rows: a group of G = 16 lanes (one DPP row) per row, four rows per wave, or for k <= 4 a
-// group of G = 4 lanes (one DPP quad) per row, sixteen rows per wave; kTileRows rows per
-// workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR
-// ranges.  For k <= 16 the group is KL = K column lanes x G/KL edge slots; for k > 16 each lane
-// owns CPL = K/16 columns at stride 16, so every load is a coalesced 64-byte segment and four rows
-// per wave stay in flight whatever k is.  A row is walked in chunks of G edges: the group loads
+// Light rows: a group of G = 16 lanes (one DPP row) per row, four rows per wave, or for k <= 8 a
+// group of G = K lanes (K = 4 or 8, k padded) per row, 16 or 8 rows per wave; kTileRows rows per
+// workgroup, rows of a group interleaved so that neighbouring groups stream adjacent CSR ranges.
+// For k <= 16 the group is KL = K column lanes x G/KL edge slots; for k > 16 each lane owns
+// CPL = K/16 columns at stride 16, so every load is a coalesced 64-byte segment and four rows per
+// wave stay in flight.  A row is walked in chunks of G edges: the group loads
 // the chunk's neighbour ids and weights with one coalesced load (lane l takes edge l), the loading
 // lane turns each id into byte offsets into U and V once, DPP broadcasts hand offsets and
 // weights to the lanes that need them, and every gather of the chunk is issued before any is
@@ -272,12 +278,12 @@ constexpr int light_cpl() {
     return K > 16 ? K / 16 : 1;
 }
 
-// Lanes per row group: 16, or 4 for k <= 4, where a 16-lane group would hold 4 edge slots of 4
-// columns and repeat the row's own power and sums in every slot; 4-lane groups take one edge at a
-// time and keep 16 rows per wave in flight.
+// Lanes per row group: 16, or K for K = 4 and 8, where a 16-lane group would hold 16 / K edge slots
+// of K columns and repeat the row's own power and sums in every slot; K-lane groups take one edge at
+// a time and keep 64 / K rows per wave in flight.
 template <int K>
 constexpr int light_group() {
-    return K <= 4 ? 4 : 16;
+    return K <= 4 ? 4 : (K == 8 ? 8 : 16);
 }
 
 // Batches in which the light kernel issues and consumes the gathers of one chunk of G edges: all at
