@@ -126,6 +126,30 @@ def test_degree_order_ragged_last_tile(k):
     gu.check(gu.compare(g, k, 1.05, 1e-8, torch.float64, dg=dg), torch.float64)
 
 
+@pytest.mark.parametrize("k", [3, 4, 8, 16, 32])
+def test_gather_floor_visits_every_edge_once(k):
+    """The gather-floor reference pass (the edge kernels with the arithmetic replaced by plain sums)
+    adds each visited entry's weight into the row's first output, so that output must equal the row
+    sums of w in every column: every stored entry visited exactly once by the light groups (4-, 8-
+    and 16-lane), the heavy chunks and the split-row combine, on the hub graph (light, single-chunk
+    and split rows) and on R-MAT-14 (degree-ordered tiles)."""
+    for g in (_hub_graph(), gen.rmat(14, 16, 0.57, 0.19, 0.19, 0.1, 1.0, seed=9)):
+        print(f"[case] gather floor {g.name} k={k}", flush=True)
+        dg = gu.device_graph(g, k)
+        U, V = gu.inputs(g.n, k)
+        _, G = pspec.hvp_gather_floor(dg, torch.as_tensor(U).cuda(), torch.as_tensor(V).cuda())
+        torch.cuda.synchronize()
+        w = g.w.astype(np.float64)
+        rows = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+        want = np.bincount(rows, weights=w, minlength=g.n)
+        got = G.double().cpu().numpy()
+        # FP32 sums of at most a few thousand positive terms in some order
+        bound = 1e-6 * np.bincount(rows, weights=np.abs(w), minlength=g.n)[:, None] * np.log2(2 + np.diff(g.rowptr))[:, None]
+        err = np.abs(got - want[:, None])
+        assert np.all(err <= bound + 1e-30), (g.name, k, float(np.max(err - bound)))
+        dg.close()
+
+
 def test_fp64_degree_order_on_uniform_graph():
     """Near-uniform degrees (SBM, n = 3,000, a ragged last tile): FP32 calls keep node order, FP64
     calls take degree order, both from the same handle; grad+HVP, objective and the Riemannian call
