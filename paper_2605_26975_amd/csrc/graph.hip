@@ -120,38 +120,48 @@ __global__ __launch_bounds__(kBlock) void k_upper_long(const int64_t *__restrict
                                                      int64_t *__restrict__ ustart, int *__restrict__ flag) {
     __shared__ int64_t s_low[kBlock / 64];
     __shared__ int s_bad[kBlock / 64];
+    __shared__ int s_long[kBlock];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // workgroup b takes rows b, b + grid, ...: long rows, which cluster at the ids of hubs, spread
-    // over the whole grid
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int64_t beg = rowptr[i], end = rowptr[i + 1];  // uniform over the workgroup
-        if (end - beg <= kUpperShort) continue;
-        int64_t low = 0;
-        int bad = 0;
-        for (int64_t q = beg + tid; q < end; q += kBlock) {
-            const int32_t c = col[q];
-            low += c <= (int32_t)i;
-            if (q + 1 < end && col[q + 1] < c) bad = 1;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
-        const bool wbad = __any(bad);
-        if (lane == 0) {
-            s_low[w] = low;
-            s_bad[w] = wbad ? 1 : 0;
-        }
+    // over the whole grid.  It first marks which of its next kBlock rows are long, one row per
+    // thread, and then walks only those.
+    const int64_t grid = gridDim.x;
+    for (int64_t r0 = blockIdx.x; r0 < n; r0 += grid * kBlock) {
+        const int64_t mine = r0 + (int64_t)tid * grid;
+        s_long[tid] = mine < n && rowptr[mine + 1] - rowptr[mine] > kUpperShort;
         __syncthreads();
-        if (tid == 0) {
-            int64_t tot = 0;
-            int bb = 0;
-            for (int v = 0; v < kBlock / 64; ++v) {
-                tot += s_low[v];
-                bb |= s_bad[v];
+        for (int t = 0; t < kBlock; ++t) {
+            if (!s_long[t]) continue;  // the same for the whole workgroup
+            const int64_t i = r0 + (int64_t)t * grid;
+            const int64_t beg = rowptr[i], end = rowptr[i + 1];
+            int64_t low = 0;
+            int bad = 0;
+            for (int64_t q = beg + tid; q < end; q += kBlock) {
+                const int32_t c = col[q];
+                low += c <= (int32_t)i;
+                if (q + 1 < end && col[q + 1] < c) bad = 1;
             }
-            ustart[i] = beg + tot;
-            if (bb) atomicOr(flag, 4);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) low += __shfl_xor(low, o);
+            const bool wbad = __any(bad);
+            if (lane == 0) {
+                s_low[w] = low;
+                s_bad[w] = wbad ? 1 : 0;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int64_t tot = 0;
+                int bb = 0;
+                for (int v = 0; v < kBlock / 64; ++v) {
+                    tot += s_low[v];
+                    bb |= s_bad[v];
+                }
+                ustart[i] = beg + tot;
+                if (bb) atomicOr(flag, 4);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        __syncthreads();  // s_long is rewritten by the next round
     }
 }
 
