@@ -129,9 +129,10 @@ pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *
  *                   validating the CSR and to read back the sizes of the schedule.
  *   out             receives the handle (a small host object).
  * Rows are binned by degree: rows with at most PSPEC_LIGHT_MAX neighbours are processed by a
- * 16-lane group per row (4 lanes for k <= 4, 8 for k <= 8), in node order or in degree order within each 256-row tile (rows of equal
- * degree by their count of entries above the diagonal; FP64 calls always in degree order; see
- * pspec_graph_degree_order); rows of up to PSPEC_CHUNK edges are one chunk each, handed
+ * 16-lane group per row (4 lanes for k <= 4, 8 for k <= 8), in node order or in degree order
+ * within each 256-row tile (rows of equal degree by their count of entries above the diagonal;
+ * FP64 calls always in degree order; see pspec_graph_degree_order); rows of up to PSPEC_CHUNK
+ * edges are one chunk each, handed
  * out in a fixed order to one wavefront each; longer rows are cut at 8 column-segment boundaries
  * (node-id ranges holding equal shares of the stored entries) and each piece into chunks of at
  * most PSPEC_CHUNK edges, the chunks of segment s going to the workgroups that run on XCD s, and
