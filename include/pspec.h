@@ -135,8 +135,9 @@ pspec_status pspec_graph_exact_workspace(int64_t n, int64_t nnz, const int64_t *
  * edges are one chunk each, handed
  * out in a fixed order to one wavefront each; longer rows are cut at 8 column-segment boundaries
  * (node-id ranges holding equal shares of the stored entries) and each piece into chunks of at
- * most PSPEC_CHUNK edges, the chunks of segment s going to the workgroups that run on XCD s, and
- * such rows are combined in a fixed order afterwards, so every result is bit-reproducible.  Any
+ * most PSPEC_CHUNK edges, the chunks of segment s going to the workgroups that run on XCD s (the
+ * objective walks all chunks with one stride), and such rows are combined in a fixed order
+ * afterwards, so every result is bit-reproducible.  Any
  * column order within a row is valid; ascending columns (the usual CSR) let each XCD's L2 cache
  * the neighbour rows of one segment only, and let pspec_objective visit each undirected edge once
  * (pspec_graph_ascending).  The CSR is validated on the device (rowptr monotone with
